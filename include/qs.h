@@ -1,0 +1,301 @@
+/*
+ * qs.h -- C ABI of libqs: a fused, LDS-blocked state-vector simulator hot
+ * path for AMD MI355X (gfx950).
+ *
+ * The method is the cache-aware state-vector simulation of arXiv 2406.14084
+ * ("Queen"): gates are grouped into gate blocks whose qubits fit in an
+ * on-chip chunk (Sec. IV, Eq. 5-7, Alg. 1-2), qubit-reorder swaps bring the
+ * qubits a block needs into its chunk (Sec. II-B Eq. 4, Sec. V-B Alg. 4), and
+ * every chunk is staged on chip once per block while all of the block's gates
+ * are applied to it (Sec. V-A, Alg. 3).
+ *
+ * Conventions used by every entry point:
+ *   - State: 2^n amplitudes a_i (Eq. 1), interleaved (re, im), complex128
+ *     (16 B) or complex64 (8 B).  Qubit q is bit q of the index (q0 = LSB).
+ *   - A k-qubit gate on targets t[0..k-1] is a 2^k x 2^k complex128 matrix,
+ *     row-major, interleaved (re, im); bit (k-1-j) of the local row/column
+ *     index is the bit of qubit t[j] (t[0] is the most significant, as in
+ *     Eq. 3 where the first listed qubit is CNOT's control).
+ *   - Memory: the caller (PyTorch) owns the state vector and any output
+ *     buffer.  The library never frees them.  Plans and handles are owned
+ *     by the library and freed with qs_plan_free / qs_destroy.
+ *   - Errors: every call returns a qs_status; on failure nothing is written
+ *     to outputs and qs_last_error() gives a message (thread-local).  No call
+ *     throws or aborts across the ABI.
+ *   - Asynchrony: device work is queued on the stream given to qs_attach;
+ *     calls that return host values synchronise that stream.
+ */
+#ifndef QS_H
+#define QS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define QS_API __attribute__((visibility("default")))
+#else
+#define QS_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { QS_C128 = 0, QS_C64 = 1 } qs_dtype;
+
+typedef enum {
+    QS_OK = 0,
+    QS_EINVAL = -1,        /* bad argument: target out of range or repeated, k outside 1..5, n outside 1..34, size mismatch */
+    QS_ENOMEM = -2,        /* host or device allocation failed */
+    QS_EHIP = -3,          /* a HIP runtime call failed; qs_last_error() has its text */
+    QS_EUNSUPPORTED = -4,  /* valid request this build does not implement */
+    QS_ESTATE = -5         /* handle not attached, or plan and state disagree on n or dtype */
+} qs_status;
+
+typedef struct qs_state qs_state;
+typedef struct qs_plan qs_plan;
+typedef struct qs_costmodel qs_costmodel;
+
+/* A circuit: an ordered gate list (the paper's raw circuit, one gate per
+ * line, Sec. VI / artifact "[Gate type] [Target qubits] [ID]"), with an
+ * explicit matrix per gate.
+ *   k[g]            number of qubits of gate g, 1..5
+ *   targets[5*g+j]  qubit t[j] of gate g (j < k[g]; other slots ignored)
+ *   matrices        the gates' matrices back to back: gate g's 2^k x 2^k
+ *                   complex128 matrix (2 * 4^k doubles) follows gate g-1's. */
+typedef struct {
+    int n;
+    int ngates;
+    const int *k;
+    const int *targets;
+    const double *matrices;
+} qs_circuit;
+
+/* Planner options (the paper's optimizer arguments: cache size C, fusion
+ * size F and the on/off switches of its artifact command line). */
+typedef struct {
+    int chunk_qubits;     /* C: qubits per on-chip chunk; 0 = default for the dtype (12 for complex128, 13 for complex64) */
+    int low_qubits;       /* L: lowest physical qubits always in the chunk (contiguous 2^L-amplitude runs); 0 = default (4) */
+    int enable_swaps;     /* 1: reorder qubits between blocks (folded into block write-back, or standalone swap passes) */
+    int enable_fusion;    /* 1: fuse gates inside a block into <= kmax-qubit unitaries / merged diagonals */
+    int planner;          /* 0 = heuristic (gate-count objective, Eq. 7); 1 = learned cost model; 2 = gate-by-gate (no blocking) */
+    const qs_costmodel *cost_model;  /* required when planner == 1, else NULL */
+    qs_dtype dtype;       /* precision the plan will run at (matrices are rounded once, after FP64 composition) */
+    int reg_qubits;       /* r: register-resident qubits per thread (4 or 5); 0 = default */
+} qs_plan_opts;
+
+/* One Pauli string times a real coefficient.  Per qubit q the letter is
+ * (bit q of xmask, bit q of zmask): (0,0)=I, (1,0)=X, (0,1)=Z, (1,1)=Y.
+ * Requires n <= 64. */
+typedef struct {
+    uint64_t xmask;
+    uint64_t zmask;
+    double coeff;
+} qs_pauli;
+
+/* Summary of a plan (algorithmic figures, independent of timing). */
+typedef struct {
+    int n;
+    int dtype;
+    int gates;            /* gates in the input circuit */
+    int blocks;           /* gate blocks = HBM passes that apply gates */
+    int swap_passes;      /* HBM passes that only permute qubits */
+    int ops;              /* fused ops over all blocks */
+    int ops_dense[6];     /* dense ops by qubit count (index 1..5) */
+    int ops_diag;         /* diagonal ops (merged diagonals) */
+    int phases;           /* register phases over all blocks (LDS exchanges) */
+    int chunk_qubits;
+    int low_qubits;
+    int reg_qubits;
+    double flops_per_amp; /* sum over ops of algorithmic flops per amplitude (dense k: 8*2^k, diagonal: 6) */
+    double hbm_bytes;     /* (blocks + swap_passes) * 2 * 2^n * bytes per amplitude */
+    double plan_seconds;  /* host time spent in qs_fuse */
+} qs_plan_stats;
+
+/* ---- state handles ------------------------------------------------------ */
+
+/* Create a handle for an n-qubit state of the given dtype (1 <= n <= 34).
+ * The handle owns no state memory until qs_attach.  Paper: Sec. III (2^N
+ * amplitudes; here one device holds all of them). */
+QS_API qs_status qs_create(int n, qs_dtype dtype, qs_state **out);
+
+/* Bind caller-owned device memory of exactly 2^n amplitudes (bytes =
+ * 2^n * 16 or 2^n * 8, 256-byte aligned) and a hipStream_t (NULL = default
+ * stream) to the handle.  The memory stays the caller's. */
+QS_API qs_status qs_attach(qs_state *st, void *amps_dev, size_t bytes, void *hip_stream);
+
+/* Free the handle (not the attached memory). */
+QS_API qs_status qs_destroy(qs_state *st);
+
+/* |0...0>: a_0 = 1, all others 0 (Alg. 3 input).  Async. */
+QS_API qs_status qs_init_zero(qs_state *st);
+
+/* |i>: a_i = 1, all others 0.  Async. */
+QS_API qs_status qs_init_basis(qs_state *st, uint64_t index);
+
+/* ---- gate-by-gate path -------------------------------------------------- */
+
+/* Apply one k-qubit gate (1 <= k <= 5) with one full pass over the state
+ * (Eq. 2, Eq. 3; the gate-by-gate scheme the paper compares against).
+ * targets: host array of k distinct qubits; matrix: host, 2 * 4^k doubles,
+ * copied before return.  Async. */
+QS_API qs_status qs_apply_gate(qs_state *st, int k, const int *targets, const double *matrix);
+
+/* In-memory swap of qubit sets (Eq. 4, Alg. 4): exchange index bits a[j] and
+ * b[j] for j < s (all 2s qubits distinct, s <= 8).  One pass.  Async. */
+QS_API qs_status qs_swap_qubits(qs_state *st, int s, const int *a, const int *b);
+
+/* ---- planner and blocked path ------------------------------------------- */
+
+/* Plan a circuit (host only; copies everything it reads): classify gates,
+ * find gate blocks at chunk size C with qubit-reorder swaps (Alg. 1-2),
+ * fuse gates inside each block into ops of at most kmax qubits (1..5)
+ * composed in FP64 (Alg. 2 level 3), and schedule each block's ops into
+ * register phases.  opts may be NULL (defaults).  The plan does not depend
+ * on any state handle; *out is freed with qs_plan_free. */
+QS_API qs_status qs_fuse(const qs_circuit *circ, int kmax, const qs_plan_opts *opts, qs_plan **out);
+
+/* Run a plan on a state (Alg. 3): for each step, one blocked pass or one
+ * swap pass over HBM.  The state is left in canonical qubit order.  The
+ * first call uploads the plan's tables to the device (synchronously).
+ * Async afterwards. */
+QS_API qs_status qs_apply_plan(qs_state *st, const qs_plan *plan);
+
+/* Same as qs_apply_plan, but records a hipEvent on the bound stream before
+ * and after every step and returns each step's device time in ms (ms_out:
+ * host array of at least the plan's step count).  *kinds_out (optional)
+ * gets 1 for a gate block, 0 for a swap pass.  Synchronises the stream. */
+QS_API qs_status qs_apply_plan_timed(qs_state *st, const qs_plan *plan, float *ms_out, int *kinds_out, int cap);
+
+/* Release a plan and its device tables. */
+QS_API qs_status qs_plan_free(qs_plan *plan);
+
+/* Text form of the plan in the spirit of the paper's optimized-circuit file:
+ * per step a count line then the step's lines ("SWAP ...", "BLOCK ...",
+ * "PHASE ...", "U<k> ..."/"D<k> ..." with physical local targets and source
+ * gate ids).  Writes at most len bytes including the NUL; *needed gets the
+ * full size.  Host only. */
+QS_API qs_status qs_plan_dump(const qs_plan *plan, char *buf, size_t len, size_t *needed);
+
+/* Fill *out with the plan's summary.  Host only. */
+QS_API qs_status qs_plan_get_stats(const qs_plan *plan, qs_plan_stats *out);
+
+/* Detailed per-block structure for tests and for the cost model:
+ * for block b (0-based in step order, swap passes excluded),
+ * phys[0..C-1] = physical qubits of the chunk, gate_ids = the original gate
+ * indices the block applies (in execution order).  Returns QS_EINVAL when b
+ * is out of range.  *ngids gets the count; at most cap ids are written. */
+QS_API qs_status qs_plan_block(const qs_plan *plan, int b, int *phys, int *gate_ids, int cap, int *ngids);
+
+/* Logical->physical qubit map in force before each step (perm[q] = physical
+ * position of logical qubit q), for step s of the plan's nsteps (swap and
+ * block steps counted together); s == nsteps gives the final map (identity).
+ * *nsteps may be NULL. */
+QS_API qs_status qs_plan_layout(const qs_plan *plan, int s, int *perm, int *nsteps);
+
+/* The encoded device program of a plan, for host-side inspection (tests
+ * replay it on the CPU to check every index the blocked kernel forms).
+ * words: int32 program of all steps back to back (*nwords of them, at most
+ * cap written); offsets: start word of each step (*nsteps, at most
+ * cap_steps written).  *r and *C receive the register and chunk widths the
+ * program was encoded for.  Host only. */
+QS_API qs_status qs_plan_program(const qs_plan *plan, int32_t *words, size_t cap, size_t *nwords,
+                                 int64_t *offsets, int cap_steps, int *nsteps, int *r, int *C,
+                                 double *mats, size_t cap_mats, size_t *nmats);
+
+/* ---- readout ------------------------------------------------------------- */
+
+/* p_i = |a_i|^2 for all i, FP64, into caller device memory out_dev (2^n
+ * doubles).  Paper: Eq. 1.  Async. */
+QS_API qs_status qs_probs(qs_state *st, double *out_dev);
+
+/* sum_t coeff_t <psi|P_t|psi> over nterms Pauli strings (FP64 accumulation),
+ * written to *out_host.  Synchronises the stream. */
+QS_API qs_status qs_expect(qs_state *st, int nterms, const qs_pauli *terms, double *out_host);
+
+/* ---- batched QAOA (many small uneven circuits in one launch) ------------- */
+
+/* Descriptor of one MaxCut QAOA instance: n qubits (2..20), nedges edges
+ * (u, v) at edges[2*e], p layers with angles gammas[l], betas[l].  Circuit:
+ * |+>^n, then per layer a_z *= exp(-i gamma C(z)) (C = cut size) and RX(2 beta)
+ * on every qubit; output <C> in FP64. */
+typedef struct {
+    int n;
+    int nedges;
+    int p;
+    const int *edges;
+    const double *gammas;
+    const double *betas;
+} qs_qaoa_instance;
+
+typedef struct qs_batch qs_batch;
+
+/* Pack count instances into device tables and size the launch (tile and
+ * chunk choices come from qs_autotune's table when given, else defaults).
+ * dtype: QS_C64 (complex64 state, FP64 reductions) or QS_C128.
+ * hip_stream: stream for all work.  Allocates device memory for the tables
+ * and the per-instance states (workspace), owned by the batch. */
+QS_API qs_status qs_batch_qaoa_create(int count, const qs_qaoa_instance *inst, qs_dtype dtype,
+                               void *hip_stream, qs_batch **out);
+
+/* Run every instance in one persistent launch; out_dev: count doubles of
+ * <C> in device memory (caller-owned).  use_graph = 1 replays a captured
+ * hipGraph of the launch (captured on first use).  Async. */
+QS_API qs_status qs_batch_qaoa_run(qs_batch *b, double *out_dev, int use_graph);
+
+/* Reference schedule: one launch per instance, in sequence (same kernels,
+ * same results), for comparison.  Async. */
+QS_API qs_status qs_batch_qaoa_run_sequential(qs_batch *b, double *out_dev);
+
+QS_API qs_status qs_batch_free(qs_batch *b);
+
+/* Choose tile/chunk parameters for the batched kernel by timing candidates
+ * on the device for the given batch; writes the chosen config index and
+ * leaves it in force for later runs of this batch.  Synchronises. */
+QS_API qs_status qs_batch_autotune(qs_batch *b, int *chosen, double *best_ms);
+
+/* ---- learned cost model (48 -> 128 -> 128 -> 1, FP32) --------------------- */
+
+#define QS_COST_FEATURES 48
+
+/* Create a model with He-uniform weights from the given seed, on the device
+ * (allocates parameters, Adam moments and a minibatch workspace). */
+QS_API qs_status qs_costmodel_create(uint64_t seed, void *hip_stream, qs_costmodel **out);
+QS_API qs_status qs_costmodel_free(qs_costmodel *m);
+
+/* Copy the parameters (FP32, order W1[128x48], b1[128], W2[128x128], b2[128],
+ * W3[1x128], b3[1], row-major) out to host / in from host; 22913 floats. */
+QS_API qs_status qs_costmodel_get_params(const qs_costmodel *m, float *host_out);
+QS_API qs_status qs_costmodel_set_params(qs_costmodel *m, const float *host_in);
+
+/* One training step on a minibatch of B rows (B <= 1024): X_dev (B x 48 FP32,
+ * device), y_dev (B FP32 targets, device): forward, MSE loss, backward
+ * (gradients kept on device), Adam update (lr, beta1 = 0.9, beta2 = 0.999,
+ * eps = 1e-8).  *loss_host gets the minibatch loss before the update if not
+ * NULL (then the call synchronises). */
+QS_API qs_status qs_costmodel_train_step(qs_costmodel *m, const float *X_dev, const float *y_dev, int B,
+                                  float lr, float *loss_host);
+
+/* Forward only: y_dev[b] = model(X_dev[b]) for B rows (device pointers). */
+QS_API qs_status qs_costmodel_predict(const qs_costmodel *m, const float *X_dev, float *y_dev, int B);
+
+/* Gradients of the last train step (same layout as the parameters). */
+QS_API qs_status qs_costmodel_get_grads(const qs_costmodel *m, float *host_out);
+
+/* Features of every block of a plan (B x 48 FP32, host), for training and
+ * for the learned planner; *nblocks gets B (at most cap rows written). */
+QS_API qs_status qs_plan_block_features(const qs_plan *plan, float *host_out, int cap, int *nblocks);
+
+/* ---- misc ---------------------------------------------------------------- */
+
+/* Message of the last failed call on this thread ("" if none). */
+QS_API const char *qs_last_error(void);
+
+/* Library version string. */
+QS_API const char *qs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QS_H */

@@ -1,0 +1,966 @@
+// planner.cpp -- host planner of libqs: gate-block finding with qubit-reorder
+// swaps, fusion inside blocks, and register-phase scheduling.
+//
+// Paper: Sec. IV (Eq. 5-7, Alg. 1 findGBs, Alg. 2 all-in-one optimisation).
+//   Level "cache" (Alg. 2, second level): gate blocks whose qubits fit in a
+//   chunk of C qubits (Eq. 5); blocks partition the gate list (Eq. 6); the
+//   objective is few blocks, i.e. many gates per block (Eq. 7).  Here a
+//   chunk is not the C lowest qubits but the L lowest physical qubits plus
+//   any C-L others, gathered as 2^(C-L) runs of 2^L contiguous amplitudes,
+//   so a block can cover high qubits without a swap pass.
+//   Qubit reordering (Sec. II-B Eq. 4, Sec. V-B): a block may write its chunk
+//   back with its bits permuted ("folded" swap, free), choosing which logical
+//   qubits occupy the always-resident low positions for the next blocks;
+//   standalone permutation passes restore canonical order at the end.
+//   Level "fusion" (Alg. 2, third level): inside a block, gates are merged
+//   into unitaries of at most kmax qubits (composed in FP64) when that does
+//   not raise the arithmetic per amplitude; diagonal gates merge into one
+//   diagonal (the paper's "D4" ops).
+//   Register phases (Sec. V-A "multiple states per thread"): each block is
+//   cut into phases; in a phase every thread keeps 2^r amplitudes whose
+//   local indices differ in r chosen chunk bits, and every dense op of the
+//   phase acts on those bits only, so it runs from registers.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <sstream>
+
+#include "qs_internal.h"
+
+namespace qs {
+
+namespace {
+
+struct GateIn {
+    int k;
+    int t[5];
+    std::vector<cplx> m;   // circuit convention: index bit (k-1-j) <-> t[j]
+    bool diag;
+};
+
+bool matrix_is_diag(const std::vector<cplx> &m, int d)
+{
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c)
+            if (r != c && m[r * d + c] != cplx(0, 0)) return false;
+    return true;
+}
+
+int popc(uint32_t x) { return __builtin_popcount(x); }
+
+// ---------------------------------------------------------------------------
+// Gate-block finding (Alg. 1 behaviour)
+// ---------------------------------------------------------------------------
+struct Blocker {
+    const std::vector<GateIn> &g;
+    int n;
+    std::vector<int> stamp;   // per qubit: == cur -> blocked in this scan
+    int cur = 0;
+
+    Blocker(const std::vector<GateIn> &gates, int nq) : g(gates), n(nq), stamp(nq, 0) {}
+
+    // Number of remaining gates executable in order with qubit set inS;
+    // optionally collects them.  A gate that cannot run blocks its qubits.
+    int count(const std::vector<int> &rem, const std::vector<char> &inS, int nS, std::vector<int> *take)
+    {
+        ++cur;
+        int cnt = 0, nblockedS = 0;
+        for (int idx : rem) {
+            const GateIn &G = g[idx];
+            bool ok = true;
+            for (int j = 0; j < G.k; ++j) {
+                int q = G.t[j];
+                if (!inS[q] || stamp[q] == cur) { ok = false; break; }
+            }
+            if (ok) {
+                ++cnt;
+                if (take) take->push_back(idx);
+            } else {
+                for (int j = 0; j < G.k; ++j) {
+                    int q = G.t[j];
+                    if (stamp[q] != cur) {
+                        stamp[q] = cur;
+                        if (inS[q]) ++nblockedS;
+                    }
+                }
+                if (nblockedS == nS) break;
+            }
+        }
+        return cnt;
+    }
+};
+
+// Greedy choice of the chunk's logical qubit set S (|S| = C) containing the
+// forced set F, maximising the number of executable gates; then a
+// one-exchange local search.
+std::vector<char> choose_chunk(Blocker &B, const std::vector<int> &rem, const std::vector<int> &forced, int C,
+                               int n)
+{
+    std::vector<char> inS(n, 0);
+    int nS = 0;
+    for (int q : forced) { inS[q] = 1; ++nS; }
+    // first pending gate index per qubit (tie-break: earlier is better)
+    std::vector<int> first(n, 1 << 30);
+    for (size_t i = 0; i < rem.size(); ++i) {
+        const GateIn &G = B.g[rem[i]];
+        for (int j = 0; j < G.k; ++j) first[G.t[j]] = std::min(first[G.t[j]], (int)i);
+    }
+    while (nS < C) {
+        int best = -1, bestc = -1, bestf = 1 << 30;
+        for (int q = 0; q < n; ++q) {
+            if (inS[q]) continue;
+            inS[q] = 1;
+            int c = B.count(rem, inS, nS + 1, nullptr);
+            inS[q] = 0;
+            if (c > bestc || (c == bestc && first[q] < bestf)) { best = q; bestc = c; bestf = first[q]; }
+        }
+        inS[best] = 1;
+        ++nS;
+    }
+    // local search: exchange one free member with one outsider while it helps
+    std::vector<char> isF(n, 0);
+    for (int q : forced) isF[q] = 1;
+    int curc = B.count(rem, inS, nS, nullptr);
+    for (int round = 0; round < 2; ++round) {
+        bool improved = false;
+        for (int a = 0; a < n && !improved; ++a) {
+            if (!inS[a] || isF[a]) continue;
+            for (int b = 0; b < n; ++b) {
+                if (inS[b]) continue;
+                inS[a] = 0; inS[b] = 1;
+                int c = B.count(rem, inS, nS, nullptr);
+                if (c > curc) { curc = c; improved = true; break; }
+                inS[a] = 1; inS[b] = 0;
+            }
+        }
+        if (!improved) break;
+    }
+    return inS;
+}
+
+// ---------------------------------------------------------------------------
+// Matrices on sets of local bits.  A "set op" holds a matrix whose index bit
+// i corresponds to the i-th lowest bit of `mask` (a mask of chunk bits).
+// ---------------------------------------------------------------------------
+struct SetOp {
+    bool diag = false;
+    uint32_t mask = 0;           // local chunk bits
+    std::vector<cplx> m;         // dense: d*d; diag: d
+    std::vector<int> gate_ids;
+};
+
+int pext(uint32_t v, uint32_t mask)
+{
+    int r = 0, i = 0;
+    for (int b = 0; b < 32; ++b)
+        if (mask >> b & 1) { r |= (int)((v >> b) & 1) << i; ++i; }
+    return r;
+}
+uint32_t pdep(int v, uint32_t mask)
+{
+    uint32_t r = 0;
+    int i = 0;
+    for (int b = 0; b < 32; ++b)
+        if (mask >> b & 1) { r |= (uint32_t)((v >> i) & 1) << b; ++i; }
+    return r;
+}
+
+// Dense matrix of op on mask U (U must contain op.mask).
+std::vector<cplx> embed_dense(const SetOp &op, uint32_t U)
+{
+    int dU = 1 << popc(U);
+    std::vector<cplx> out((size_t)dU * dU, cplx(0, 0));
+    int d = 1 << popc(op.mask);
+    uint32_t rest = U & ~op.mask;
+    for (int u = 0; u < dU; ++u) {
+        uint32_t gu = pdep(u, U);
+        int ru = pext(gu, op.mask);
+        for (int v = 0; v < dU; ++v) {
+            uint32_t gv = pdep(v, U);
+            if ((gu & rest) != (gv & rest)) continue;
+            int rv = pext(gv, op.mask);
+            if (op.diag) {
+                if (ru == rv) out[(size_t)u * dU + v] = op.m[ru];
+            } else {
+                out[(size_t)u * dU + v] = op.m[(size_t)ru * d + rv];
+            }
+        }
+    }
+    (void)d;
+    return out;
+}
+
+std::vector<cplx> matmul(const std::vector<cplx> &A, const std::vector<cplx> &B, int d)
+{
+    std::vector<cplx> C((size_t)d * d, cplx(0, 0));
+    for (int i = 0; i < d; ++i)
+        for (int k = 0; k < d; ++k) {
+            cplx a = A[(size_t)i * d + k];
+            if (a == cplx(0, 0)) continue;
+            for (int j = 0; j < d; ++j) C[(size_t)i * d + j] += a * B[(size_t)k * d + j];
+        }
+    return C;
+}
+
+// later o applied after earlier e: result = o * e on the union.
+SetOp compose(const SetOp &e, const SetOp &o)
+{
+    SetOp r;
+    r.mask = e.mask | o.mask;
+    r.gate_ids = e.gate_ids;
+    r.gate_ids.insert(r.gate_ids.end(), o.gate_ids.begin(), o.gate_ids.end());
+    if (e.diag && o.diag) {
+        r.diag = true;
+        int d = 1 << popc(r.mask);
+        r.m.resize(d);
+        for (int u = 0; u < d; ++u) {
+            uint32_t gu = pdep(u, r.mask);
+            r.m[u] = o.m[pext(gu, o.mask)] * e.m[pext(gu, e.mask)];
+        }
+        return r;
+    }
+    r.diag = false;
+    int d = 1 << popc(r.mask);
+    r.m = matmul(embed_dense(o, r.mask), embed_dense(e, r.mask), d);
+    return r;
+}
+
+double op_cost(bool diag, int k) { return diag ? 5.0 : 4.0 * (double)(1 << k); }
+
+// Convert a circuit gate to a set op over local bits (loc[j] = local bit of t[j]).
+SetOp gate_to_setop(const GateIn &G, const int *loc, int gid)
+{
+    SetOp s;
+    s.diag = G.diag;
+    s.gate_ids.push_back(gid);
+    for (int j = 0; j < G.k; ++j) s.mask |= 1u << loc[j];
+    int d = 1 << G.k;
+    // circuit index bit (k-1-j) <-> t[j] <-> local bit loc[j]; set-op index bit i <-> i-th lowest local bit
+    auto conv = [&](int ci) {
+        uint32_t g = 0;
+        for (int j = 0; j < G.k; ++j)
+            if ((ci >> (G.k - 1 - j)) & 1) g |= 1u << loc[j];
+        return pext(g, s.mask);
+    };
+    std::vector<int> map(d);
+    for (int ci = 0; ci < d; ++ci) map[ci] = conv(ci);
+    if (s.diag) {
+        s.m.assign(d, cplx(0, 0));
+        for (int ci = 0; ci < d; ++ci) s.m[map[ci]] = G.m[(size_t)ci * d + ci];
+    } else {
+        s.m.assign((size_t)d * d, cplx(0, 0));
+        for (int r = 0; r < d; ++r)
+            for (int c = 0; c < d; ++c) s.m[(size_t)map[r] * d + map[c]] = G.m[(size_t)r * d + c];
+    }
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// Register phases for one block
+// ---------------------------------------------------------------------------
+struct PhaseSched {
+    int C, r, L, kmax;
+    bool fuse;
+
+    // count executable ops with register set Rmask; dense ops need mask subset.
+    int count(const std::vector<SetOp> &rem, uint32_t Rmask, std::vector<int> *take) const
+    {
+        uint32_t blocked = 0;
+        int cnt = 0;
+        for (size_t i = 0; i < rem.size(); ++i) {
+            const SetOp &o = rem[i];
+            bool ok = !(o.mask & blocked) && (o.diag || (o.mask & ~Rmask) == 0);
+            if (ok) {
+                ++cnt;
+                if (take) take->push_back((int)i);
+            } else {
+                blocked |= o.mask;
+                if ((blocked & Rmask) == Rmask && Rmask) {
+                    // every register bit blocked: only diagonals on free bits can still run
+                }
+            }
+        }
+        return cnt;
+    }
+
+    uint32_t choose_R(const std::vector<SetOp> &rem, uint32_t allowed) const
+    {
+        uint32_t R = 0;
+        int nR = 0;
+        // earliest pending dense op's bits as tie-break order
+        std::vector<int> first(C, 1 << 30);
+        for (size_t i = 0; i < rem.size(); ++i)
+            if (!rem[i].diag)
+                for (int b = 0; b < C; ++b)
+                    if (rem[i].mask >> b & 1) first[b] = std::min(first[b], (int)i);
+        int avail = popc(allowed);
+        int want = std::min(r, avail);
+        while (nR < want) {
+            int best = -1, bestc = -1, bestf = 1 << 30;
+            for (int b = 0; b < C; ++b) {
+                if (!(allowed >> b & 1) || (R >> b & 1)) continue;
+                int c = count(rem, R | (1u << b), nullptr);
+                if (c > bestc || (c == bestc && first[b] < bestf)) { best = b; bestc = c; bestf = first[b]; }
+            }
+            R |= 1u << best;
+            ++nR;
+        }
+        return R;
+    }
+
+    // fuse the ops of one phase (in order) under register set R.
+    //  - a dense op merges into the single op that last touched its bits when
+    //    the union stays in registers, within kmax, and costs no more;
+    //  - a diagonal op merges into the dense op that last touched its bits if
+    //    they are a subset, otherwise into the latest diagonal op F such that
+    //    every op after F that shares its bits is itself diagonal (diagonals
+    //    commute), as long as the merged diagonal has at most kMaxDiagBits bits.
+    std::vector<SetOp> fuse_phase(const std::vector<SetOp> &ops, uint32_t R) const
+    {
+        std::vector<SetOp> out;
+        std::vector<int> owner(C, -1);
+        auto set_owner = [&](uint32_t mask, int idx) {
+            for (int b = 0; b < C; ++b)
+                if ((mask >> b & 1) && owner[b] < idx) owner[b] = idx;
+        };
+        for (const SetOp &o : ops) {
+            int F = -2;  // -2: none yet; -1: conflicting owners
+            for (int b = 0; b < C; ++b) {
+                if (!(o.mask >> b & 1) || owner[b] < 0) continue;
+                if (F == -2) F = owner[b];
+                else if (F != owner[b]) F = -1;
+            }
+            int merged_into = -1;
+            if (fuse && F >= 0) {
+                SetOp &f = out[F];
+                uint32_t U = f.mask | o.mask;
+                int kU = popc(U);
+                double before = op_cost(f.diag, popc(f.mask)) + op_cost(o.diag, popc(o.mask));
+                bool ok;
+                if (f.diag && o.diag) ok = kU <= kMaxDiagBits;
+                else if (!f.diag && o.diag) ok = (o.mask & ~f.mask) == 0;
+                else ok = (U & ~R) == 0 && kU <= kmax && op_cost(false, kU) <= before;
+                if (ok) {
+                    f = compose(f, o);
+                    merged_into = F;
+                }
+            }
+            if (fuse && merged_into < 0 && o.diag) {
+                // latest diagonal F with only diagonals after it on o's bits
+                for (int i = (int)out.size() - 1; i >= 0; --i) {
+                    if (out[i].diag) {
+                        if (popc(out[i].mask | o.mask) <= kMaxDiagBits) {
+                            out[i] = compose(out[i], o);
+                            merged_into = i;
+                        }
+                        break;
+                    }
+                    if (out[i].mask & o.mask) break;   // a dense op on o's bits: cannot pass it
+                }
+            }
+            if (merged_into >= 0) {
+                set_owner(o.mask, merged_into);
+            } else {
+                out.push_back(o);
+                set_owner(o.mask, (int)out.size() - 1);
+            }
+        }
+        return out;
+    }
+};
+
+Op to_kernel_op(const SetOp &s, const Layout &lay, int r)
+{
+    Op op;
+    op.gate_ids = s.gate_ids;
+    op.k = popc(s.mask);
+    op.m = s.m;
+    if (s.diag) {
+        op.kind = OP_DIAG;
+        int i = 0;
+        for (int b = 0; b < 32; ++b)
+            if (s.mask >> b & 1) op.tl[i++] = b;
+    } else {
+        op.kind = OP_DENSE;
+        int mask = 0;
+        for (int j = 0; j < r; ++j)
+            if (s.mask >> lay.R[j] & 1) mask |= 1 << j;
+        op.regmask = mask;
+    }
+    return op;
+}
+
+Layout make_layout(uint32_t Rmask, int C, int r, const std::vector<int> *store_order)
+{
+    Layout lay;
+    int i = 0;
+    for (int b = 0; b < C; ++b)
+        if (Rmask >> b & 1) lay.R[i++] = b;
+    int t = 0;
+    if (store_order) {
+        for (int b : *store_order)
+            if (!(Rmask >> b & 1)) lay.T[t++] = b;
+    } else {
+        for (int b = 0; b < C; ++b)
+            if (!(Rmask >> b & 1)) lay.T[t++] = b;
+    }
+    (void)r;
+    return lay;
+}
+
+
+// A pass that only permutes: W = physical positions of the chunk (size C,
+// containing 0..L-1), target_pos[i] = new position of the amplitude bit now at W[i].
+Block make_perm_block(int C, int r, int L, const std::vector<int> &W, const std::vector<int> &target_pos)
+{
+    Block blk;
+    blk.permute_only = true;
+    std::vector<std::pair<int, int>> pr;
+    for (size_t i = 0; i < W.size(); ++i) pr.push_back({W[i], target_pos[i]});
+    std::sort(pr.begin(), pr.end());
+    for (auto &x : pr) { blk.P_in.push_back(x.first); blk.P_out.push_back(x.second); }
+    std::vector<int> store_order(C);
+    std::iota(store_order.begin(), store_order.end(), 0);
+    std::sort(store_order.begin(), store_order.end(), [&](int a, int b) { return blk.P_out[a] < blk.P_out[b]; });
+    uint32_t lowmask_out = 0;
+    for (int i = 0; i < L; ++i) lowmask_out |= 1u << store_order[i];
+    uint32_t lowmask_in = (L > 0) ? ((1u << L) - 1) : 0;
+    // one layout serves load and store when both use the same low local bits and the
+    // registers avoid them; otherwise a load phase and a store phase with one exchange
+    uint32_t R = 0;
+    int cnt = 0;
+    for (int b = C - 1; b >= 0 && cnt < r; --b)
+        if (!(lowmask_in >> b & 1) && !(lowmask_out >> b & 1)) { R |= 1u << b; ++cnt; }
+    if (cnt == r && lowmask_in == lowmask_out) {
+        Phase ph;
+        ph.lay = make_layout(R, C, r, &store_order);
+        blk.phases.push_back(ph);
+    } else {
+        uint32_t R0 = 0, R1 = 0;
+        int c0 = 0, c1 = 0;
+        for (int b = C - 1; b >= 0 && c0 < r; --b)
+            if (!(lowmask_in >> b & 1)) { R0 |= 1u << b; ++c0; }
+        for (int b = C - 1; b >= 0 && c1 < r; --b)
+            if (!(lowmask_out >> b & 1)) { R1 |= 1u << b; ++c1; }
+        Phase ld, st;
+        ld.lay = make_layout(R0, C, r, nullptr);
+        st.lay = make_layout(R1, C, r, &store_order);
+        blk.phases.push_back(ld);
+        blk.phases.push_back(st);
+    }
+    return blk;
+}
+
+}  // namespace
+
+// Plan for a standalone in-memory swap (Eq. 4): exchange physical bits a[j] <-> b[j].
+qs_status build_swap_plan(int n, qs_dtype dtype, int s, const int *a, const int *b, Plan *p, std::string *err)
+{
+    if (n < 1 || n > 34 || s < 0 || s > 32) { *err = "qs_swap_qubits: bad n or s"; return QS_EINVAL; }
+    uint64_t used = 0;
+    for (int j = 0; j < s; ++j) {
+        if (a[j] < 0 || a[j] >= n || b[j] < 0 || b[j] >= n || a[j] == b[j] || (used >> a[j] & 1) || (used >> b[j] & 1)) {
+            *err = "qs_swap_qubits: qubits must be distinct and in range";
+            return QS_EINVAL;
+        }
+        used |= (1ull << a[j]) | (1ull << b[j]);
+    }
+    p->n = n;
+    p->dtype = dtype;
+    int r = (dtype == QS_C64) ? 5 : 4;
+    int C = std::min((dtype == QS_C64) ? 13 : 12, n);
+    r = std::min(r, C);
+    int L = std::min(4, C - r);
+    p->C = C; p->r = r; p->L = L;
+    p->blocks.clear();
+    int j = 0;
+    while (j < s) {
+        std::vector<char> inW(n, 0);
+        std::vector<int> W;
+        for (int q = 0; q < L; ++q) { inW[q] = 1; W.push_back(q); }
+        std::vector<int> tgt_of(n, -1);
+        while (j < s) {
+            int need = (!inW[a[j]]) + (!inW[b[j]]);
+            if ((int)W.size() + need > C) break;
+            if (!inW[a[j]]) { inW[a[j]] = 1; W.push_back(a[j]); }
+            if (!inW[b[j]]) { inW[b[j]] = 1; W.push_back(b[j]); }
+            tgt_of[a[j]] = b[j];
+            tgt_of[b[j]] = a[j];
+            ++j;
+        }
+        for (int q = n - 1; q >= 0 && (int)W.size() < C; --q)
+            if (!inW[q]) { inW[q] = 1; W.push_back(q); }
+        std::vector<int> tgt(W.size());
+        for (size_t i = 0; i < W.size(); ++i) tgt[i] = (tgt_of[W[i]] >= 0) ? tgt_of[W[i]] : W[i];
+        p->blocks.push_back(make_perm_block(C, r, L, W, tgt));
+    }
+    encode_plan(p);
+    return QS_OK;
+}
+
+namespace {
+}  // namespace
+
+// ---------------------------------------------------------------------------
+qs_status build_plan(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan *p, std::string *err)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (!c || c->n < 1 || c->n > 34 || c->ngates < 0 || (c->ngates > 0 && (!c->k || !c->targets || !c->matrices))) {
+        *err = "qs_fuse: bad circuit (n must be 1..34, arrays non-null)";
+        return QS_EINVAL;
+    }
+    if (kmax < 1 || kmax > 5) { *err = "qs_fuse: kmax must be 1..5"; return QS_EINVAL; }
+    qs_plan_opts opts{};
+    if (o) opts = *o;
+    else { opts.enable_swaps = 1; opts.enable_fusion = 1; }
+    if (opts.dtype != QS_C128 && opts.dtype != QS_C64) { *err = "qs_fuse: bad dtype"; return QS_EINVAL; }
+    const int n = c->n;
+    p->n = n;
+    p->dtype = opts.dtype;
+    p->ngates = c->ngates;
+    p->kmax = kmax;
+
+    // ---- gates
+    std::vector<GateIn> gates(c->ngates);
+    const double *mp = c->matrices;
+    int maxk = 1;
+    for (int g = 0; g < c->ngates; ++g) {
+        GateIn &G = gates[g];
+        G.k = c->k[g];
+        if (G.k < 1 || G.k > 5 || G.k > n) { *err = "qs_fuse: gate " + std::to_string(g) + " has bad k"; return QS_EINVAL; }
+        uint64_t seen = 0;
+        for (int j = 0; j < G.k; ++j) {
+            int q = c->targets[5 * g + j];
+            if (q < 0 || q >= n || (seen >> q & 1)) {
+                *err = "qs_fuse: gate " + std::to_string(g) + " has a bad or repeated target";
+                return QS_EINVAL;
+            }
+            seen |= 1ull << q;
+            G.t[j] = q;
+        }
+        int d = 1 << G.k;
+        G.m.resize((size_t)d * d);
+        for (int i = 0; i < d * d; ++i) G.m[i] = cplx(mp[2 * i], mp[2 * i + 1]);
+        mp += 2 * (size_t)d * d;
+        G.diag = matrix_is_diag(G.m, d);
+        if (!G.diag) maxk = std::max(maxk, G.k);
+    }
+
+    // ---- geometry
+    int r = opts.reg_qubits ? opts.reg_qubits : (opts.dtype == QS_C64 ? 5 : 4);
+    if (r < 1 || r > kMaxReg) { *err = "qs_fuse: reg_qubits must be 1..5"; return QS_EINVAL; }
+    r = std::max(r, maxk);                     // a dense gate must fit in registers
+    int C = opts.chunk_qubits ? opts.chunk_qubits : (opts.dtype == QS_C64 ? 13 : 12);
+    if (C < 1 || C > kMaxChunk) { *err = "qs_fuse: chunk_qubits must be 1..14"; return QS_EINVAL; }
+    int L = opts.low_qubits ? opts.low_qubits : 4;
+    C = std::min(C, n);
+    r = std::min(r, C);
+    if (maxk > r) { *err = "qs_fuse: a gate is wider than the chunk"; return QS_EINVAL; }
+    if (C - r > 10) { *err = "qs_fuse: chunk_qubits - reg_qubits must be <= 10 (1024 threads)"; return QS_EINVAL; }
+    L = std::min(L, C - r);                    // low qubits live in thread bits of load/store layouts
+    if (L < 0) L = 0;
+    p->C = C; p->r = r; p->L = L;
+    const int kf = std::min(kmax, r);
+    const bool gbg = (opts.planner == 2);
+
+    // ---- blocking with reorder swaps
+    std::vector<int> l2p(n), p2l(n);
+    std::iota(l2p.begin(), l2p.end(), 0);
+    std::iota(p2l.begin(), p2l.end(), 0);
+    std::vector<int> rem(c->ngates);
+    std::iota(rem.begin(), rem.end(), 0);
+    Blocker B(gates, n);
+    PhaseSched PS{C, r, L, kf, opts.enable_fusion != 0};
+
+    auto emit_block = [&](const std::vector<char> &inS, const std::vector<int> &take, bool last) {
+        Block blk;
+        // chunk positions = physical positions of S
+        for (int q = 0; q < n; ++q)
+            if (inS[q]) blk.P_in.push_back(l2p[q]);
+        std::sort(blk.P_in.begin(), blk.P_in.end());
+        std::vector<int> loc_of_phys(n, -1);
+        for (int b = 0; b < C; ++b) loc_of_phys[blk.P_in[b]] = b;
+        p->layouts.push_back(l2p);
+        // ops in local bits
+        std::vector<SetOp> ops;
+        for (int gi : take) {
+            const GateIn &G = gates[gi];
+            int loc[5];
+            for (int j = 0; j < G.k; ++j) loc[j] = loc_of_phys[l2p[G.t[j]]];
+            ops.push_back(gate_to_setop(G, loc, gi));
+            blk.gate_ids.push_back(gi);
+        }
+        // ---- output placement (folded swap)
+        std::vector<int> newpos(C);   // local bit b (logical p2l[P_in[b]]) -> physical
+        for (int b = 0; b < C; ++b) newpos[b] = blk.P_in[b];
+        if (opts.enable_swaps) {
+            // members of S by next use after this block
+            std::vector<int> done_mark(c->ngates, 0);
+            for (int gi : take) done_mark[gi] = 1;
+            std::vector<int> nextuse(n, 1 << 30);
+            int pos = 0;
+            for (int gi : rem) {
+                if (done_mark[gi]) continue;
+                for (int j = 0; j < gates[gi].k; ++j) {
+                    int q = gates[gi].t[j];
+                    nextuse[q] = std::min(nextuse[q], pos);
+                }
+                ++pos;
+            }
+            std::vector<int> locs(C);
+            std::iota(locs.begin(), locs.end(), 0);
+            if (last) {
+                // put every logical qubit home when its home is in the chunk
+                std::vector<int> free_pos;
+                std::vector<char> placed(C, 0);
+                std::vector<char> taken(n, 0);
+                for (int b = 0; b < C; ++b) {
+                    int q = p2l[blk.P_in[b]];
+                    if (loc_of_phys[q] >= 0) { newpos[b] = q; placed[b] = 1; taken[q] = 1; }
+                }
+                for (int b = 0; b < C; ++b)
+                    if (!taken[blk.P_in[b]]) free_pos.push_back(blk.P_in[b]);
+                size_t fi = 0;
+                for (int b = 0; b < C; ++b)
+                    if (!placed[b]) newpos[b] = free_pos[fi++];
+            } else {
+                // the L soonest-needed qubits go to physical 0..L-1
+                std::stable_sort(locs.begin(), locs.end(), [&](int a, int b) {
+                    return nextuse[p2l[blk.P_in[a]]] < nextuse[p2l[blk.P_in[b]]];
+                });
+                std::vector<char> isLow(C, 0);
+                for (int i = 0; i < L; ++i) isLow[locs[i]] = 1;
+                // low slots: keep a chosen qubit where it is if already low
+                std::vector<int> lowfree;
+                std::vector<char> placed(C, 0);
+                for (int b = 0; b < L; ++b) {  // local b < L is physical b
+                    if (isLow[b]) { newpos[b] = blk.P_in[b]; placed[b] = 1; }
+                    else lowfree.push_back(blk.P_in[b]);
+                }
+                std::vector<int> highfree;
+                for (int b = L; b < C; ++b) {
+                    if (!isLow[b]) { newpos[b] = blk.P_in[b]; placed[b] = 1; }
+                }
+                size_t li = 0;
+                for (int b = L; b < C; ++b)
+                    if (isLow[b]) { highfree.push_back(blk.P_in[b]); newpos[b] = lowfree[li++]; placed[b] = 1; }
+                size_t hi = 0;
+                for (int b = 0; b < L; ++b)
+                    if (!placed[b]) { newpos[b] = highfree[hi++]; placed[b] = 1; }
+            }
+        }
+        blk.P_out = newpos;
+        // update maps
+        std::vector<int> movedq(C);
+        for (int b = 0; b < C; ++b) movedq[b] = p2l[blk.P_in[b]];
+        for (int b = 0; b < C; ++b) { l2p[movedq[b]] = newpos[b]; p2l[newpos[b]] = movedq[b]; }
+
+        // ---- phases
+        std::vector<int> store_order;   // local bits ordered by output physical position
+        {
+            std::vector<int> lb(C);
+            std::iota(lb.begin(), lb.end(), 0);
+            std::sort(lb.begin(), lb.end(), [&](int a, int b) { return newpos[a] < newpos[b]; });
+            store_order = lb;
+        }
+        uint32_t lowmask_in = (L > 0) ? ((1u << L) - 1) : 0;      // local bits at physical 0..L-1 on load
+        uint32_t lowmask_out = 0;
+        for (int i = 0; i < L; ++i) lowmask_out |= 1u << store_order[i];
+        uint32_t all = (C >= 32) ? 0xffffffffu : ((1u << C) - 1);
+        std::vector<SetOp> prem = ops;
+        bool first = true;
+        while (!prem.empty() || first) {
+            uint32_t allowed = first ? (all & ~lowmask_in) : all;
+            uint32_t R = PS.choose_R(prem, allowed);
+            std::vector<int> takeidx;
+            PS.count(prem, R, &takeidx);
+            std::vector<SetOp> phase_ops;
+            std::vector<char> used(prem.size(), 0);
+            for (int i : takeidx) { phase_ops.push_back(prem[i]); used[i] = 1; }
+            std::vector<SetOp> rest;
+            for (size_t i = 0; i < prem.size(); ++i)
+                if (!used[i]) rest.push_back(prem[i]);
+            prem.swap(rest);
+            Phase ph;
+            ph.lay = make_layout(R, C, r, nullptr);
+            for (const SetOp &s : PS.fuse_phase(phase_ops, R)) ph.ops.push_back(to_kernel_op(s, ph.lay, r));
+            blk.phases.push_back(ph);
+            first = false;
+        }
+        // store layout: registers away from the output-low bits, thread bits in output order
+        {
+            Phase &lastp = blk.phases.back();
+            uint32_t Rl = 0;
+            for (int j = 0; j < r; ++j) Rl |= 1u << lastp.lay.R[j];
+            if ((Rl & lowmask_out) || (blk.phases.size() == 1 && lowmask_out != lowmask_in)) {
+                // choose the r highest output positions that are not low
+                uint32_t R = 0;
+                int cnt = 0;
+                for (int i = C - 1; i >= 0 && cnt < r; --i) {
+                    int b = store_order[i];
+                    if (!(lowmask_out >> b & 1)) { R |= 1u << b; ++cnt; }
+                }
+                Phase sp;
+                sp.lay = make_layout(R, C, r, &store_order);
+                blk.phases.push_back(sp);
+            } else {
+                lastp.lay = make_layout(Rl, C, r, &store_order);
+                // ops of the last phase index registers by R, which is unchanged
+            }
+        }
+        p->blocks.push_back(std::move(blk));
+    };
+
+    auto emit_perm_pass = [&](const std::vector<int> &W, const std::vector<int> &target_pos) {
+        p->layouts.push_back(l2p);
+        Block blk = make_perm_block(C, r, L, W, target_pos);
+        std::vector<int> movedq(C);
+        for (int b = 0; b < C; ++b) movedq[b] = p2l[blk.P_in[b]];
+        for (int b = 0; b < C; ++b) { l2p[movedq[b]] = blk.P_out[b]; p2l[blk.P_out[b]] = movedq[b]; }
+        p->blocks.push_back(std::move(blk));
+    };
+
+    if (gbg) {
+        // one block per gate: the gate's qubits plus the resident low qubits
+        for (int gi = 0; gi < c->ngates; ++gi) {
+            std::vector<char> inS(n, 0);
+            int nS = 0;
+            for (int j = 0; j < gates[gi].k; ++j) { inS[gates[gi].t[j]] = 1; ++nS; }
+            for (int pp = 0; pp < L; ++pp)
+                if (!inS[p2l[pp]]) { inS[p2l[pp]] = 1; ++nS; }
+            for (int pp = 0; pp < n && nS < C; ++pp)
+                if (!inS[p2l[pp]]) { inS[p2l[pp]] = 1; ++nS; }
+            std::vector<int> take{gi};
+            rem.erase(rem.begin());
+            emit_block(inS, take, false);
+        }
+    } else {
+        while (!rem.empty()) {
+            std::vector<int> forced;
+            for (int pp = 0; pp < L; ++pp) forced.push_back(p2l[pp]);
+            std::vector<char> inS = choose_chunk(B, rem, forced, C, n);
+            int nS = C;
+            std::vector<int> take;
+            B.count(rem, inS, nS, &take);
+            if (take.empty()) { *err = "qs_fuse: internal error: empty gate block"; return QS_EINVAL; }
+            // is this the last block?
+            bool last = (take.size() == rem.size());
+            std::vector<char> dm(c->ngates, 0);
+            for (int gi : take) dm[gi] = 1;
+            emit_block(inS, take, last);
+            std::vector<int> nr;
+            for (int gi : rem)
+                if (!dm[gi]) nr.push_back(gi);
+            rem.swap(nr);
+        }
+    }
+    // ---- restore canonical order with permutation passes
+    for (int guard = 0; guard < 4 * n + 8; ++guard) {
+        std::vector<int> disp;
+        for (int pp = 0; pp < n; ++pp)
+            if (p2l[pp] != pp) disp.push_back(pp);
+        if (disp.empty()) break;
+        // follow cycles to collect up to C - L positions (plus the low ones)
+        std::vector<char> inW(n, 0);
+        std::vector<int> W;
+        for (int pp = 0; pp < L; ++pp) { inW[pp] = 1; W.push_back(pp); }
+        std::vector<char> seen(n, 0);
+        for (int start : disp) {
+            if ((int)W.size() >= C) break;
+            int x = start;
+            while (!seen[x] && (int)W.size() < C) {
+                seen[x] = 1;
+                if (!inW[x]) { inW[x] = 1; W.push_back(x); }
+                x = p2l[x];      // the qubit at x wants to go home to position p2l[x]
+                if (x == start) break;
+            }
+        }
+        for (int pp = 0; pp < n && (int)W.size() < C; ++pp)
+            if (!inW[pp]) { inW[pp] = 1; W.push_back(pp); }
+        std::vector<int> tgt(W.size(), -1);
+        std::vector<char> used(n, 0);
+        for (size_t i = 0; i < W.size(); ++i) {
+            int q = p2l[W[i]];
+            if (inW[q]) { tgt[i] = q; used[q] = 1; }
+        }
+        std::vector<int> freep;
+        for (int x : W)
+            if (!used[x]) freep.push_back(x);
+        size_t fi = 0;
+        for (size_t i = 0; i < W.size(); ++i)
+            if (tgt[i] < 0) tgt[i] = freep[fi++];
+        emit_perm_pass(W, tgt);
+    }
+    p->layouts.push_back(l2p);
+    for (int q = 0; q < n; ++q)
+        if (l2p[q] != q) { *err = "qs_fuse: internal error: final layout not canonical"; return QS_EINVAL; }
+
+    // ---- stats
+    qs_plan_stats &s = p->stats;
+    std::memset(&s, 0, sizeof(s));
+    s.n = n;
+    s.dtype = opts.dtype;
+    s.gates = c->ngates;
+    s.chunk_qubits = C;
+    s.low_qubits = L;
+    s.reg_qubits = r;
+    for (const Block &blk : p->blocks) {
+        if (blk.permute_only) ++s.swap_passes;
+        else ++s.blocks;
+        for (const Phase &ph : blk.phases) {
+            ++s.phases;
+            for (const Op &op : ph.ops) {
+                ++s.ops;
+                if (op.kind == OP_DIAG) { ++s.ops_diag; s.flops_per_amp += 6.0; }
+                else { ++s.ops_dense[op.k]; s.flops_per_amp += 8.0 * (double)(1 << op.k); }
+            }
+        }
+    }
+    double amp_bytes = (opts.dtype == QS_C64) ? 8.0 : 16.0;
+    s.hbm_bytes = (double)(s.blocks + s.swap_passes) * 2.0 * std::ldexp(1.0, n) * amp_bytes;
+    encode_plan(p);
+    p->plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    s.plan_seconds = p->plan_seconds;
+    return QS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Encoding for the blocked kernel
+// ---------------------------------------------------------------------------
+namespace {
+// Low-nibble images of local bits under swizzle nibbles F.
+uint32_t img(int b, const uint32_t *F) { return b < 4 ? (1u << b) : F[b - 4]; }
+
+bool independent4(uint32_t a, uint32_t b, uint32_t c, uint32_t d)
+{
+    uint32_t v[4] = {a, b, c, d};
+    // span check over GF(2): all 16 XOR combinations distinct
+    uint32_t seen = 0;
+    for (int s = 0; s < 16; ++s) {
+        uint32_t x = 0;
+        for (int i = 0; i < 4; ++i)
+            if (s >> i & 1) x ^= v[i];
+        if (seen >> x & 1) return false;
+        seen |= 1u << x;
+    }
+    return true;
+}
+
+uint64_t choose_swizzle(const Layout &from, const Layout &to, int C, int r)
+{
+    int tb = C - r;
+    if (tb < 4 || C <= 4) return 0;
+    uint32_t F[16] = {0};
+    uint64_t rng = 0x9E3779B97F4A7C15ull ^ (uint64_t)(from.T[0] * 131 + to.T[0] * 17 + C);
+    auto next = [&]() { rng ^= rng << 13; rng ^= rng >> 7; rng ^= rng << 17; return rng; };
+    bool inset[32] = {false};
+    for (int i = 0; i < 4; ++i) { inset[from.T[i]] = true; inset[to.T[i]] = true; }
+    for (int tries = 0; tries < 4000; ++tries) {
+        bool ok1 = independent4(img(from.T[0], F), img(from.T[1], F), img(from.T[2], F), img(from.T[3], F));
+        bool ok2 = independent4(img(to.T[0], F), img(to.T[1], F), img(to.T[2], F), img(to.T[3], F));
+        if (ok1 && ok2) break;
+        for (int b = 4; b < C; ++b) F[b - 4] = inset[b] ? (uint32_t)(next() & 15) : 0;
+    }
+    uint64_t w = 0;
+    for (int b = 4; b < C; ++b) w |= (uint64_t)(F[b - 4] & 15) << (4 * (b - 4));
+    return w;
+}
+}  // namespace
+
+void encode_plan(Plan *p)
+{
+    p->h_prog.clear();
+    p->h_mats.clear();
+    p->prog_off.clear();
+    const int C = p->C, r = p->r;
+    for (const Block &blk : p->blocks) {
+        int64_t start = (int64_t)p->h_prog.size();
+        p->prog_off.push_back(start);
+        std::vector<int32_t> w;
+        w.push_back((int32_t)blk.phases.size());
+        w.push_back(C);
+        w.push_back(r);
+        w.push_back(blk.permute_only ? 1 : 0);
+        for (int b = 0; b < C; ++b) w.push_back(blk.P_in[b]);
+        for (int b = 0; b < C; ++b) w.push_back(blk.P_out[b]);
+        std::vector<std::pair<size_t, std::vector<int>>> diag_fix;   // (word index of aux, bits)
+        for (size_t ph = 0; ph < blk.phases.size(); ++ph) {
+            const Phase &P = blk.phases[ph];
+            uint64_t swz = (ph > 0) ? choose_swizzle(blk.phases[ph - 1].lay, P.lay, C, r) : 0;
+            w.push_back((int32_t)P.ops.size());
+            w.push_back((int32_t)(uint32_t)(swz & 0xffffffffu));
+            w.push_back((int32_t)(uint32_t)(swz >> 32));
+            w.push_back(0);
+            for (int j = 0; j < r; ++j) w.push_back(P.lay.R[j]);
+            for (int j = 0; j < C - r; ++j) w.push_back(P.lay.T[j]);
+            for (const Op &op : P.ops) {
+                int64_t moff = (int64_t)p->h_mats.size();
+                for (const cplx &z : op.m) { p->h_mats.push_back(z.real()); p->h_mats.push_back(z.imag()); }
+                int variant = (op.kind == OP_DENSE) ? op.regmask : 0;
+                w.push_back(op.kind | (variant << 8) | (op.k << 16));
+                w.push_back((int32_t)(uint32_t)(moff & 0xffffffff));
+                w.push_back((int32_t)(uint32_t)(moff >> 32));
+                w.push_back(0);
+                if (op.kind == OP_DIAG) diag_fix.push_back({w.size() - 1, std::vector<int>(op.tl, op.tl + op.k)});
+            }
+        }
+        for (auto &df : diag_fix) {
+            w[df.first] = (int32_t)w.size();
+            for (int b : df.second) w.push_back(b);
+        }
+        p->h_prog.insert(p->h_prog.end(), w.begin(), w.end());
+    }
+    if (p->dtype == QS_C64) {
+        p->h_mats32.resize(p->h_mats.size());
+        for (size_t i = 0; i < p->h_mats.size(); ++i) p->h_mats32[i] = (float)p->h_mats[i];
+    }
+    if (p->h_mats.empty()) p->h_mats.push_back(0.0);
+    if (p->h_prog.empty()) p->h_prog.push_back(0);
+    if (p->dtype == QS_C64 && p->h_mats32.empty()) p->h_mats32.push_back(0.f);
+}
+
+// ---------------------------------------------------------------------------
+std::string dump_plan(const Plan &p)
+{
+    std::ostringstream os;
+    os.precision(17);
+    os << "# n=" << p.n << " C=" << p.C << " L=" << p.L << " r=" << p.r << " kmax=" << p.kmax
+       << " dtype=" << (p.dtype == QS_C64 ? "c64" : "c128") << "\n";
+    for (size_t bi = 0; bi < p.blocks.size(); ++bi) {
+        const Block &b = p.blocks[bi];
+        int lines = 1;
+        for (const Phase &ph : b.phases) lines += 1 + (int)ph.ops.size();
+        os << lines << "\n";
+        os << (b.permute_only ? "SWAP" : "BLOCK") << " in";
+        for (int x : b.P_in) os << " " << x;
+        os << " out";
+        for (int x : b.P_out) os << " " << x;
+        os << "\n";
+        for (const Phase &ph : b.phases) {
+            os << "PHASE R";
+            for (int j = 0; j < p.r; ++j) os << " " << ph.lay.R[j];
+            os << " T";
+            for (int j = 0; j < p.C - p.r; ++j) os << " " << ph.lay.T[j];
+            os << "\n";
+            for (const Op &op : ph.ops) {
+                if (op.kind == OP_DIAG) {
+                    os << "D" << op.k;
+                    for (int j = 0; j < op.k; ++j) os << " " << op.tl[j];
+                    os << " " << op.m[0].real() << " " << op.m[0].imag();
+                } else {
+                    os << "U" << op.k;
+                    for (int j = 0; j < p.r; ++j)
+                        if (op.regmask >> j & 1) os << " " << ph.lay.R[j];
+                }
+                os << " ids";
+                for (int g : op.gate_ids) os << " " << g;
+                os << "\n";
+            }
+        }
+    }
+    return os.str();
+}
+
+}  // namespace qs

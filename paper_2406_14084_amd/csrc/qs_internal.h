@@ -1,0 +1,147 @@
+// qs_internal.h -- structures shared by the host planner, the C ABI and the
+// kernel launchers of libqs.  Not installed; the public interface is
+// include/qs.h.
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/qs.h"
+
+namespace qs {
+
+using cplx = std::complex<double>;
+
+// Largest chunk (in qubits) and register-bit count the blocked kernel is
+// instantiated for.
+constexpr int kMaxChunk = 14;
+constexpr int kMaxReg = 5;
+constexpr int kMaxDiagBits = 8;   // merged diagonals keep at most 2^8 entries
+
+// ---------------------------------------------------------------------------
+// Plan IR (host side)
+// ---------------------------------------------------------------------------
+enum OpKind { OP_DENSE = 0, OP_DIAG = 1 };
+
+struct Op {
+    int kind = OP_DENSE;
+    // Dense: register-position mask (bit j set = register bit j is a target);
+    //        matrix index bit i <-> the i-th lowest set bit of the mask.
+    // Diag:  local chunk bits tl[0..k-1] ascending; table index bit i <-> tl[i].
+    int regmask = 0;
+    int k = 0;
+    int tl[kMaxDiagBits] = {0};
+    std::vector<cplx> m;          // dense: (2^k)^2 row-major; diag: 2^k
+    std::vector<int> gate_ids;    // original gates folded into this op (order of application)
+};
+
+struct Layout {
+    int R[kMaxReg];               // local bits held in registers (ascending)
+    int T[kMaxChunk];             // local bits of the thread index, thread bit b <-> T[b]
+};
+
+struct Phase {
+    Layout lay;
+    std::vector<Op> ops;
+};
+
+struct Block {
+    std::vector<int> P_in;        // P_in[b]  = physical qubit of local bit b when loading (ascending)
+    std::vector<int> P_out;       // P_out[b] = physical qubit local bit b is written to (a permutation of P_in)
+    std::vector<Phase> phases;
+    std::vector<int> gate_ids;    // original gates in execution order
+    bool permute_only = false;    // a swap pass: no ops
+};
+
+struct Plan {
+    int n = 0;
+    qs_dtype dtype = QS_C128;
+    int C = 12, L = 4, r = 4;
+    int kmax = 5;
+    std::vector<Block> blocks;          // steps, in order (swap passes are blocks with permute_only)
+    std::vector<std::vector<int>> layouts;  // l2p before each step, plus the final one
+    int ngates = 0;
+    double plan_seconds = 0.0;
+    qs_plan_stats stats{};
+    std::string error;
+
+    // device tables (uploaded on first use)
+    bool uploaded = false;
+    int upload_device = -1;
+    void *d_prog = nullptr;             // int32 program words for all blocks
+    void *d_mats = nullptr;             // matrices (FP64 or FP32 by dtype)
+    std::vector<int64_t> prog_off;      // per block: offset of its program in d_prog (int32 words)
+    std::vector<int32_t> h_prog;
+    std::vector<double> h_mats;
+    std::vector<float> h_mats32;
+};
+
+// Build the plan (host).  Returns QS_OK or an error with *err filled.
+qs_status build_plan(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan *p, std::string *err);
+// Plan of permutation-only passes exchanging physical bits a[j] <-> b[j].
+qs_status build_swap_plan(int n, qs_dtype dtype, int s, const int *a, const int *b, Plan *p, std::string *err);
+// Serialise to the kernel program format (host arrays in p).
+void encode_plan(Plan *p);
+// Text dump.
+std::string dump_plan(const Plan &p);
+// Block features for the cost model (48 per block).
+void block_features(const Plan &p, std::vector<float> *out);
+
+// ---------------------------------------------------------------------------
+// Program encoding read by the blocked kernel (int32 words per block):
+//   [0] nphases, [1] C, [2] r, [3] reserved
+//   [4 .. 4+C)        P_in
+//   [4+C .. 4+2C)     P_out
+//   then per phase:
+//     [0] nops, [1] swz_lo (F nibbles for high bits 0..7), [2] swz_hi (8..15), [3] reserved
+//     [4 .. 4+r)      R
+//     [4+r .. 4+C)    T
+//     then per op: 4 words: [kind | (variant << 8) | (k << 16)] [mat_off lo] [mat_off hi] [aux]
+//       dense: variant = register mask; aux unused
+//       diag : variant = 0; aux = word offset (from block start) of k local-bit words
+// The swizzle for the exchange INTO a phase: slot(l) = l ^ F(l >> 4) where
+// F XORs nibble b of swz (bits 4b..4b+3) for every set bit b of (l >> 4).
+// ---------------------------------------------------------------------------
+enum { PROG_HDR = 4, PHASE_HDR = 4, OP_WORDS = 4 };
+
+}  // namespace qs
+
+// ---------------------------------------------------------------------------
+// State handle
+// ---------------------------------------------------------------------------
+struct qs_state {
+    int n = 0;
+    qs_dtype dtype = QS_C128;
+    void *amps = nullptr;
+    size_t bytes = 0;
+    hipStream_t stream = nullptr;
+    int device = -1;
+    void *d_scratch = nullptr;     // small device scratch: gate matrices for k >= 4, reduction partials
+    size_t scratch_bytes = 0;
+};
+
+struct qs_plan {
+    qs::Plan p;
+};
+
+// error helpers (api.cpp)
+namespace qs {
+void set_error(const std::string &msg);
+qs_status hip_fail(hipError_t e, const char *what);
+}
+
+// kernel launchers (k_basic.hip / k_block.hip)
+namespace qs {
+hipError_t launch_init(qs_state *st, uint64_t index);
+hipError_t launch_gate(qs_state *st, int k, const int *targets, const double *matrix, const void *d_matrix);
+hipError_t launch_swap(qs_state *st, int s, const int *a, const int *b);
+hipError_t launch_probs(qs_state *st, double *out);
+hipError_t launch_expect(qs_state *st, int nterms, const qs_pauli *terms, double *partials, int nparts);
+int expect_partials(int n);
+hipError_t launch_block(qs_state *st, const Plan &p, int b);
+hipError_t launch_block_prog(qs_state *st, int r, int C, const int *d_prog, const void *d_mats);
+}

@@ -1,0 +1,194 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+complex128 results must match the oracle element by element within
+max |delta amplitude| <= 1e-12 (the target stated for this path); pure data
+movement (swaps, basis states) must match bit for bit.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import sim
+from paper_2406_14084_amd import inputs as I
+from paper_2406_14084_amd import qs
+from tests.gpu_util import TOL_C128, max_abs_diff, need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return need_gpu()
+
+
+def run_plan(circ, **kw):
+    st = qs.State(circ.n, "c128")
+    st.init_zero()
+    p = qs.Plan(circ, **kw)
+    st.apply_plan(p)
+    out = st.numpy()
+    return out, p
+
+
+def test_init_basis(torch):
+    for n, idx in ((1, 0), (5, 17), (13, 8191), (20, 12345)):
+        say("init_basis", n, idx)
+        st = qs.State(n, "c128")
+        st.init_basis(idx)
+        a = st.numpy()
+        want = np.zeros(1 << n, dtype=np.complex128)
+        want[idx] = 1
+        assert np.array_equal(a, want)
+
+
+@pytest.mark.parametrize("n,seed,kmax", [(3, 1, 3), (8, 2, 3), (12, 3, 5), (17, 4, 4)])
+def test_gate_by_gate_vs_oracle(torch, n, seed, kmax):
+    c = I.random_dense(n, 40, seed, kmax=kmax)
+    say("gbg", n, seed, kmax, len(c))
+    st = qs.State(n, "c128")
+    st.init_zero()
+    st.apply_circuit_gbg(c)
+    got = st.numpy()
+    want = sim.run(c)
+    assert max_abs_diff(got, want) <= TOL_C128
+
+
+def test_layered_16q_vs_oracle(torch):
+    """16-qubit layered rotations + brickwork CX, 20 layers, seed 16001."""
+    c = I.layered_rotations(n=16, layers=20, seed=16001)
+    say("layered16 fused")
+    got, p = run_plan(c, kmax=5)
+    want = sim.run(c)
+    d = max_abs_diff(got, want)
+    assert d <= TOL_C128, (d, p.stats())
+
+
+@pytest.mark.parametrize("cfg", [
+    dict(n=10, kmax=1), dict(n=10, kmax=2), dict(n=14, kmax=3), dict(n=14, kmax=4),
+    dict(n=18, kmax=5), dict(n=18, kmax=4, swaps=False), dict(n=18, kmax=4, fusion=False),
+    dict(n=20, kmax=4, chunk_qubits=10), dict(n=20, kmax=4, chunk_qubits=11, low_qubits=3),
+    dict(n=20, kmax=5, reg_qubits=5), dict(n=16, kmax=4, chunk_qubits=8),
+    dict(n=21, kmax=3, planner=2),
+])
+def test_random_circuits_vs_oracle(torch, cfg):
+    cfg = dict(cfg)
+    n = cfg.pop("n")
+    c = I.random_dense(n, 150, seed=100 + n + cfg.get("kmax", 0), kmax=3)
+    say("random", n, cfg)
+    got, p = run_plan(c, **cfg)
+    want = sim.run(c)
+    d = max_abs_diff(got, want)
+    assert d <= TOL_C128, (d, p.stats())
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7])
+def test_small_n_vs_oracle(torch, n):
+    c = I.random_dense(n, 30, seed=n, kmax=min(3, n))
+    say("small", n)
+    got, _ = run_plan(c, kmax=min(5, n))
+    assert max_abs_diff(got, sim.run(c)) <= TOL_C128
+
+
+def test_empty_circuit(torch):
+    c = I.Circuit(12)
+    say("empty")
+    got, p = run_plan(c, kmax=4)
+    want = np.zeros(1 << 12, dtype=np.complex128)
+    want[0] = 1
+    assert np.array_equal(got, want) and p.stats()["blocks"] == 0
+
+
+def test_five_qubit_gates(torch):
+    """k = 5 dense gates need five register bits; the planner widens r."""
+    rng = np.random.default_rng(5)
+    c = I.Circuit(16)
+    for i in range(12):
+        tg = tuple(int(v) for v in rng.choice(16, size=5, replace=False))
+        c.add("U5", tg, I.g_haar(rng, 32))
+    say("k5")
+    got, p = run_plan(c, kmax=5)
+    assert p.stats()["reg_qubits"] == 5
+    assert max_abs_diff(got, sim.run(c)) <= TOL_C128
+
+
+def test_u3_cz_22q_vs_oracle(torch):
+    """The 30-qubit random U3 + CZ recipe at 22 qubits, full depth 40."""
+    c = I.random_u3_2q(n=22, depth=40, seed=22002)
+    say("u3cz22")
+    got, p = run_plan(c, kmax=5)
+    want = sim.run(c)
+    d = max_abs_diff(got, want)
+    assert d <= TOL_C128, (d, p.stats())
+
+
+def test_qft_closed_form_gpu(torch):
+    n = 18
+    x = 98765
+    c = I.qft(n)
+    say("qft", n)
+    st = qs.State(n, "c128")
+    st.init_basis(x)
+    st.apply_plan(qs.Plan(c, kmax=4))
+    got = st.numpy()
+    want = np.zeros(1 << n, dtype=np.complex128)
+    psi = np.zeros(1 << n, dtype=np.complex128)
+    psi[x] = 1
+    sim.apply_circuit(psi, c)
+    assert max_abs_diff(got, psi) <= TOL_C128
+
+
+@pytest.mark.parametrize("n,a,b", [(10, (0,), (9,)), (14, (1, 2), (13, 7)), (20, (0, 5, 9), (19, 18, 3)),
+                                   (22, (3, 4, 5, 6), (21, 20, 19, 0)), (24, (0, 1, 2, 3, 4, 5, 6, 7), (23, 22, 21, 20, 19, 18, 17, 16))])
+def test_swap_kernel_exact(torch, n, a, b):
+    rng = np.random.default_rng(n)
+    psi = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    say("swap", n, a, b)
+    st = qs.State(n, "c128")
+    st.tensor.copy_(torch.from_numpy(psi))
+    st.swap_qubits(a, b)
+    got = st.numpy()
+    want = psi.copy()
+    sim.swap_qubits(want, a, b)
+    assert np.array_equal(got, want)
+
+
+def test_probs_and_expect(torch):
+    n = 14
+    c = I.random_dense(n, 60, seed=77, kmax=3)
+    want = sim.run(c)
+    say("probs/expect")
+    st = qs.State(n, "c128")
+    st.init_zero()
+    st.apply_plan(qs.Plan(c, kmax=4))
+    p = st.probs().cpu().numpy()
+    assert np.max(np.abs(p - sim.probs(want))) <= 1e-13
+    rng = np.random.default_rng(1)
+    terms = [(int(rng.integers(1 << n)), int(rng.integers(1 << n)), float(rng.standard_normal())) for _ in range(12)]
+    terms.append((0, 0, 0.5))
+    got = st.expect(terms)
+    ref = sim.expect(want, terms)
+    assert abs(got - ref) <= 1e-12 * max(1.0, abs(ref))
+
+
+def test_u3_cz_30q_inverse_full_size(torch):
+    """Full-size check in the benchmark's launch configuration: the 30-qubit
+    depth-40 U3 + CZ circuit followed by its inverse (both fused and blocked)
+    returns |0...0>: |a_0 - 1| and the norm of everything else are tiny,
+    and the norm stays 1."""
+    c = I.random_u3_2q(n=30, depth=40, seed=30002)
+    say("u3cz30 inverse")
+    st = qs.State(30, "c128")
+    st.init_zero()
+    p1 = qs.Plan(c, kmax=5)
+    p2 = qs.Plan(c.inverse(), kmax=5)
+    st.apply_plan(p1)
+    norm1 = float(st.probs().sum().item())
+    st.apply_plan(p2)
+    t = st.tensor
+    a0 = complex(t[0].item())
+    rest = float((t[1:].abs() ** 2).sum().item())
+    assert abs(norm1 - 1.0) <= 1e-11
+    assert abs(a0 - 1.0) <= 1e-11 and math.sqrt(rest) <= 1e-11, (a0, rest)
