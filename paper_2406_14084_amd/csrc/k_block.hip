@@ -87,6 +87,16 @@ __device__ __forceinline__ uint32_t thread_local_bits(uint32_t tid, const int *_
     return l;
 }
 
+// bits of v selected by mask, packed to the low end (ascending)
+__device__ __forceinline__ uint32_t pext_u32(uint32_t v, uint32_t mask)
+{
+    uint32_t r = 0;
+    int i = 0;
+    for (int b = 0; b < 16; ++b)
+        if ((mask >> b) & 1u) { r |= ((v >> b) & 1u) << i; ++i; }
+    return r;
+}
+
 // physical offset of a local index
 __device__ __forceinline__ uint64_t local_to_phys(uint32_t l, const int *__restrict__ P, int C)
 {
@@ -198,8 +208,32 @@ __global__ __launch_bounds__(256) void k_block(typename AmpOf<F>::type *__restri
             const F *__restrict__ M = mats + moff;   // moff counts scalars
             if (kind == OP_DENSE) {
                 dense_dispatch<R, 1, F, V>(variant, v, M);
+            } else if (kind == OP_DIAG_REG) {
+                // uniform entry per register
+#pragma unroll
+                for (int m = 0; m < NR; ++m) v[m] = cmul<F, V>(M[2 * m], M[2 * m + 1], v[m]);
+            } else if (kind == OP_DIAG_ROW) {
+                // this lane's row of 2^R entries; row = the op's thread-index bits of tid
+                const uint32_t row = pext_u32(tid, (uint32_t)op[3]);
+                const F *__restrict__ E = M + (size_t)row * (2 * NR);
+#pragma unroll
+                for (int m = 0; m < NR; ++m) v[m] = cmul<F, V>(E[2 * m], E[2 * m + 1], v[m]);
+            } else if (kind == OP_SIGN_REG) {
+                const uint32_t s = (uint32_t)op[3];
+#pragma unroll
+                for (int m = 0; m < NR; ++m)
+                    if ((s >> m) & 1u) { v[m].x = -v[m].x; v[m].y = -v[m].y; }
+            } else if (kind == OP_SIGN_ROW) {
+                const uint32_t row = pext_u32(tid, (uint32_t)op[1]);
+                const uint32_t s = (uint32_t)prog[op[3] + row];
+#pragma unroll
+                for (int m = 0; m < NR; ++m) {
+                    const F sg = ((s >> m) & 1u) ? (F)-1 : (F)1;
+                    v[m].x *= sg;
+                    v[m].y *= sg;
+                }
             } else {
-                // diagonal on local bits tl[0..k-1] (ascending); entry index bit i <-> tl[i]
+                // general diagonal on local bits tl[0..k-1] (ascending); entry index bit i <-> tl[i]
                 const int *tl = prog + op[3];
                 uint32_t lt = thread_local_bits(tid, T, tb);
                 uint32_t it = 0;
@@ -222,6 +256,13 @@ __global__ __launch_bounds__(256) void k_block(typename AmpOf<F>::type *__restri
         // skip past nothing: op now points after the last op of this phase
     }
     // ---- store in the last layout, through P_out
+    if ((prog[3] & 2) && nph == 1) {
+        // No exchange (hence no barrier) separated the loads from the stores, and the
+        // write-back permutes positions: a store may target an amplitude another wave
+        // has not loaded yet.  Wait for this wave's loads, then for every wave.
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    }
     {
         const int *Rb = prev + PHASE_HDR;
         const int *T = Rb + R;

@@ -882,10 +882,13 @@ void encode_plan(Plan *p)
         w.push_back((int32_t)blk.phases.size());
         w.push_back(C);
         w.push_back(r);
-        w.push_back(blk.permute_only ? 1 : 0);
+        // flags: bit 0 = swap pass; bit 1 = the write-back moves amplitudes between
+        // threads' load positions (P_out != P_in), so loads must all complete
+        // before any store even when no exchange separates them
+        w.push_back((blk.permute_only ? 1 : 0) | (blk.P_out != blk.P_in ? 2 : 0));
         for (int b = 0; b < C; ++b) w.push_back(blk.P_in[b]);
         for (int b = 0; b < C; ++b) w.push_back(blk.P_out[b]);
-        std::vector<std::pair<size_t, std::vector<int>>> diag_fix;   // (word index of aux, bits)
+        std::vector<std::pair<size_t, std::vector<int32_t>>> tail_fix;   // (word index to patch, words to append)
         for (size_t ph = 0; ph < blk.phases.size(); ++ph) {
             const Phase &P = blk.phases[ph];
             uint64_t swz = (ph > 0) ? choose_swizzle(blk.phases[ph - 1].lay, P.lay, C, r) : 0;
@@ -895,20 +898,74 @@ void encode_plan(Plan *p)
             w.push_back(0);
             for (int j = 0; j < r; ++j) w.push_back(P.lay.R[j]);
             for (int j = 0; j < C - r; ++j) w.push_back(P.lay.T[j]);
+            const int NR = 1 << r;
             for (const Op &op : P.ops) {
                 int64_t moff = (int64_t)p->h_mats.size();
-                for (const cplx &z : op.m) { p->h_mats.push_back(z.real()); p->h_mats.push_back(z.imag()); }
-                int variant = (op.kind == OP_DENSE) ? op.regmask : 0;
-                w.push_back(op.kind | (variant << 8) | (op.k << 16));
+                if (op.kind == OP_DENSE) {
+                    for (const cplx &z : op.m) { p->h_mats.push_back(z.real()); p->h_mats.push_back(z.imag()); }
+                    w.push_back(OP_DENSE | (op.regmask << 8) | (op.k << 16));
+                    w.push_back((int32_t)(uint32_t)(moff & 0xffffffff));
+                    w.push_back((int32_t)(uint32_t)(moff >> 32));
+                    w.push_back(0);
+                    continue;
+                }
+                // diagonal: split its bits into register bits and thread bits of this layout
+                uint32_t opmask = 0;
+                for (int i = 0; i < op.k; ++i) opmask |= 1u << op.tl[i];
+                uint32_t tmask = 0;     // over thread-index bits
+                int kt = 0;
+                for (int j = 0; j < C - r; ++j)
+                    if (opmask >> P.lay.T[j] & 1) { tmask |= 1u << j; ++kt; }
+                bool sign = true;
+                for (const cplx &z : op.m)
+                    if (!(z.imag() == 0.0 && (z.real() == 1.0 || z.real() == -1.0))) { sign = false; break; }
+                // entry for (row, m): local index from the row's thread bits and m's register bits
+                auto entry = [&](int row, int m) {
+                    uint32_t l = 0;
+                    int i = 0;
+                    for (int j = 0; j < C - r; ++j)
+                        if (tmask >> j & 1) { l |= (uint32_t)((row >> i) & 1) << P.lay.T[j]; ++i; }
+                    for (int j = 0; j < r; ++j)
+                        if (m >> j & 1) l |= 1u << P.lay.R[j];
+                    int idx = 0;
+                    for (int t = 0; t < op.k; ++t) idx |= (int)((l >> op.tl[t]) & 1) << t;
+                    return op.m[idx];
+                };
+                const int rows = 1 << kt;
+                if (sign) {
+                    std::vector<int32_t> masks(rows, 0);
+                    for (int row = 0; row < rows; ++row)
+                        for (int m = 0; m < NR; ++m)
+                            if (entry(row, m).real() < 0) masks[row] |= (int32_t)(1u << m);
+                    if (kt == 0) {
+                        w.push_back(OP_SIGN_REG | (op.k << 16));
+                        w.push_back(0);
+                        w.push_back(0);
+                        w.push_back(masks[0]);
+                    } else {
+                        w.push_back(OP_SIGN_ROW | (op.k << 16));
+                        w.push_back((int32_t)tmask);
+                        w.push_back(0);
+                        w.push_back(0);
+                        tail_fix.push_back({w.size() - 1, masks});
+                    }
+                    continue;
+                }
+                for (int row = 0; row < rows; ++row)
+                    for (int m = 0; m < NR; ++m) {
+                        cplx z = entry(row, m);
+                        p->h_mats.push_back(z.real());
+                        p->h_mats.push_back(z.imag());
+                    }
+                w.push_back((kt == 0 ? OP_DIAG_REG : OP_DIAG_ROW) | (op.k << 16));
                 w.push_back((int32_t)(uint32_t)(moff & 0xffffffff));
                 w.push_back((int32_t)(uint32_t)(moff >> 32));
-                w.push_back(0);
-                if (op.kind == OP_DIAG) diag_fix.push_back({w.size() - 1, std::vector<int>(op.tl, op.tl + op.k)});
+                w.push_back((int32_t)tmask);
             }
         }
-        for (auto &df : diag_fix) {
-            w[df.first] = (int32_t)w.size();
-            for (int b : df.second) w.push_back(b);
+        for (auto &tf : tail_fix) {
+            w[tf.first] = (int32_t)w.size();
+            for (int32_t x : tf.second) w.push_back(x);
         }
         p->h_prog.insert(p->h_prog.end(), w.begin(), w.end());
     }

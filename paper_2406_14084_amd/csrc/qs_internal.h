@@ -25,7 +25,14 @@ constexpr int kMaxDiagBits = 8;   // merged diagonals keep at most 2^8 entries
 // ---------------------------------------------------------------------------
 // Plan IR (host side)
 // ---------------------------------------------------------------------------
-enum OpKind { OP_DENSE = 0, OP_DIAG = 1 };
+enum OpKind {
+    OP_DENSE = 0,      // dense 2^k x 2^k on register bits (regmask)
+    OP_DIAG = 1,       // planner form of a diagonal on local bits tl[]; encoded as one of:
+    OP_DIAG_REG = 2,   //   bits all in registers: 2^r entries in register order, uniform
+    OP_DIAG_ROW = 3,   //   some bits are thread bits: 2^kt rows of 2^r entries, row = pext(tid, tmask)
+    OP_SIGN_REG = 4,   //   entries all +-1, bits in registers: bit m of a mask negates register m
+    OP_SIGN_ROW = 5    //   entries all +-1 with thread bits: one such mask per row
+};
 
 struct Op {
     int kind = OP_DENSE;
@@ -93,16 +100,19 @@ void block_features(const Plan &p, std::vector<float> *out);
 
 // ---------------------------------------------------------------------------
 // Program encoding read by the blocked kernel (int32 words per block):
-//   [0] nphases, [1] C, [2] r, [3] reserved
+//   [0] nphases, [1] C, [2] r, [3] flags (bit 0 swap pass, bit 1 P_out != P_in)
 //   [4 .. 4+C)        P_in
 //   [4+C .. 4+2C)     P_out
 //   then per phase:
 //     [0] nops, [1] swz_lo (F nibbles for high bits 0..7), [2] swz_hi (8..15), [3] reserved
 //     [4 .. 4+r)      R
 //     [4+r .. 4+C)    T
-//     then per op: 4 words: [kind | (variant << 8) | (k << 16)] [mat_off lo] [mat_off hi] [aux]
-//       dense: variant = register mask; aux unused
-//       diag : variant = 0; aux = word offset (from block start) of k local-bit words
+//     then per op: 4 words: [kind | (variant << 8) | (k << 16)] [w1] [w2] [w3]
+//       DENSE   : variant = register mask; w1,w2 = matrix offset (scalars, lo/hi)
+//       DIAG_REG: w1,w2 = offset of 2^r entries (register order)
+//       DIAG_ROW: w1,w2 = offset of 2^kt * 2^r entries; w3 = tmask (thread-index bits of the row)
+//       SIGN_REG: w3 = mask over registers (bit m set: negate register m)
+//       SIGN_ROW: w1 = tmask; w3 = word offset (from block start) of 2^kt row masks
 // The swizzle for the exchange INTO a phase: slot(l) = l ^ F(l >> 4) where
 // F XORs nibble b of swz (bits 4b..4b+3) for every set bit b of (l >> 4).
 // ---------------------------------------------------------------------------

@@ -29,6 +29,16 @@ def _pdep(v, mask):
     return r
 
 
+def _pext(v, mask):
+    r = np.zeros_like(v)
+    i = 0
+    for b in range(16):
+        if (mask >> b) & 1:
+            r |= ((v >> b) & 1) << i
+            i += 1
+    return r
+
+
 def _thread_local(tid, T, tb):
     l = np.zeros_like(tid)
     for j in range(tb):
@@ -125,6 +135,28 @@ def replay_block(psi, w, n, R, mats):
                     res = np.einsum("rc,wtc->wtr", M, vin)
                     out[:, :, cols] = res
                 v = out
+            elif kind == 2:       # register diagonal: uniform entry per register
+                E = mats[moff:moff + 2 * NR].view(np.complex128)
+                v = v * E[None, None, :]
+            elif kind == 3:       # per-row diagonal: row = pext(tid, tmask)
+                tmask = int(w[op + 3])
+                row = _pext(tid, tmask)
+                kt = bin(tmask).count("1")
+                E = mats[moff:moff + 2 * NR * (1 << kt)].view(np.complex128).reshape(1 << kt, NR)
+                v = v * E[row][None, :, :]
+            elif kind == 4:       # +-1 on registers
+                s = int(np.uint32(w[op + 3]))
+                sg = np.array([-1.0 if (s >> m) & 1 else 1.0 for m in range(NR)])
+                v = v * sg[None, None, :]
+            elif kind == 5:       # +-1 per row
+                tmask = int(w[op + 1])
+                row = _pext(tid, tmask)
+                kt = bin(tmask).count("1")
+                a = int(w[op + 3])
+                masks = np.array([int(np.uint32(x)) for x in w[a:a + (1 << kt)]], dtype=np.int64)
+                s = masks[row]
+                sg = np.where(((s[:, None] >> np.arange(NR)[None, :]) & 1) == 1, -1.0, 1.0)
+                v = v * sg[None, :, :]
             else:
                 a = int(w[op + 3])
                 tl = [int(x) for x in w[a:a + k]]
@@ -147,6 +179,13 @@ def replay_block(psi, w, n, R, mats):
     assert np.unique(so).size == so.size == (1 << n), "store is not a bijection"
     for i in range(nwg):   # each workgroup writes exactly what it read
         assert np.array_equal(np.sort(so[i].reshape(-1)), np.sort(li[i].reshape(-1)))
+    # Without an exchange there is no barrier between loads and stores: then a
+    # thread may only overwrite positions it loaded itself, unless the program
+    # asks the kernel for a barrier (flag bit 1).
+    if nph == 1 and not (int(w[3]) & 2):
+        assert np.array_equal(np.sort(so, axis=2), np.sort(li, axis=2)), "store/load race between threads"
+    if Pin != Pout:
+        assert int(w[3]) & 2
     out = psi.copy()
     out[so] = v
     return out
@@ -167,6 +206,7 @@ def replay_plan(plan, n):
     dict(n=13, seed=5, kmax=4, swaps=False), dict(n=13, seed=6, kmax=2, fusion=False),
     dict(n=12, seed=7, kmax=5, reg_qubits=5), dict(n=11, seed=8, kmax=3, chunk_qubits=7, reg_qubits=3),
     dict(n=3, seed=9, kmax=3), dict(n=1, seed=10, kmax=1), dict(n=12, seed=11, kmax=3, planner=2),
+    dict(n=14, seed=12, kmax=4, chunk_qubits=8), dict(n=15, seed=13, kmax=2, chunk_qubits=9, low_qubits=2),
 ])
 def test_replay_matches_oracle(cfg):
     cfg = dict(cfg)
@@ -198,3 +238,45 @@ def test_replay_swap_plan_is_bit_permutation():
     p = qs.Plan(c, kmax=2)
     got = replay_plan(p, n)
     assert np.max(np.abs(got - sim.run(c))) <= 1e-15
+
+
+def test_replay_covers_folded_swaps_and_swap_passes():
+    """The configurations above include blocks whose write-back permutes
+    qubits and standalone swap passes (so the race check above is exercised)."""
+    c = I.random_dense(14, 80, 12, kmax=3)
+    p = qs.Plan(c, kmax=4, chunk_qubits=8)
+    w, offs, R, C, mats = p.program()
+    flags = [int(w[o + 3]) for o in offs]
+    assert any(f & 1 for f in flags) and any(f & 2 for f in flags)
+
+
+def test_replay_uses_every_diagonal_encoding():
+    """Circuits with general and +-1 diagonals exercise the register, row and
+    sign encodings of diagonal ops."""
+    n = 13
+    kinds = set()
+    for seed in range(4):
+        c = I.random_u3_2q(n=n, depth=6, seed=seed)
+        rng = np.random.default_rng(seed)
+        for _ in range(20):
+            a, b = (int(x) for x in rng.choice(n, 2, replace=False))
+            c.add("RZZ", (a, b), I.g_rzz(float(rng.uniform(0, 6))))
+        c2 = I.random_dense(9, 60, 50 + seed, kmax=3, kinds=("dense", "diag"))
+        for cc in (c, c2):
+            p = qs.Plan(cc, kmax=4)
+            kinds |= _op_kinds(p)
+            assert np.max(np.abs(replay_plan(p, cc.n) - sim.run(cc))) <= 1e-12
+    assert {0, 2, 3, 4, 5} <= kinds, kinds
+
+
+def _op_kinds(p):
+    kinds = set()
+    w, offs, R, C, mats = p.program()
+    for o in offs:
+            nph = int(w[o]); ph = o + PROG_HDR + 2 * C
+            for _ in range(nph):
+                nops = int(w[ph]); op = ph + PHASE_HDR + C
+                for _ in range(nops):
+                    kinds.add(int(w[op]) & 0xff); op += OP_WORDS
+                ph = op
+    return kinds
