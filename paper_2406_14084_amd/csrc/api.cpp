@@ -155,7 +155,8 @@ qs_status qs_apply_gate(qs_state *st, int k, const int *targets, const double *m
 static qs_status run_blocks(qs_state *st, const qs::Plan &p, const int *d_prog, const void *d_mats, const char *fn)
 {
     for (size_t b = 0; b < p.blocks.size(); ++b) {
-        hipError_t e = qs::launch_block_prog(st, p.r, p.C, d_prog + p.prog_off[b], d_mats);
+        const size_t tab = (size_t)p.h_prog[p.prog_off[b] + 5] * 4;
+        hipError_t e = qs::launch_block_prog(st, p.r, p.C, d_prog + p.prog_off[b], d_mats, tab, p.block_kmax[b]);
         if (e != hipSuccess) return hip_fail(e, fn);
     }
     return QS_OK;

@@ -19,6 +19,8 @@
 //     are register bits;
 //   - the write-back may permute the chunk's bits (P_out), which performs a
 //     qubit swap at no extra HBM pass.
+#include <algorithm>
+
 #include "amp.h"
 #include "qs_internal.h"
 
@@ -66,17 +68,31 @@ __device__ __forceinline__ void apply_dense(V (&v)[1 << R], const F *__restrict_
     }
 }
 
-template <int R, int MASK, typename F, typename V>
+// Runs the dense op whose register mask equals `mask`; only masks of at most
+// KMAX bits are compiled in (the planner picks the variant wide enough for
+// its ops, which keeps register pressure low for plans of narrow ops).
+#define QS_DENSE_CASE(MM)                                                                 \
+    case MM:                                                                              \
+        if constexpr ((MM) < (1 << R) && __builtin_popcount(MM) <= KMAX)                  \
+            apply_dense<R, ((MM) < (1 << R) ? (MM) : 1), F, V>(v, M);                      \
+        break;
+
+template <int R, int KMAX, typename F, typename V>
 __device__ __forceinline__ void dense_dispatch(int mask, V (&v)[1 << R], const F *__restrict__ M)
 {
-    if constexpr (MASK < (1 << R)) {
-        if (mask == MASK) {
-            apply_dense<R, MASK, F, V>(v, M);
-            return;
-        }
-        dense_dispatch<R, MASK + 1, F, V>(mask, v, M);
+    switch (mask) {
+        QS_DENSE_CASE(1) QS_DENSE_CASE(2) QS_DENSE_CASE(3) QS_DENSE_CASE(4) QS_DENSE_CASE(5)
+        QS_DENSE_CASE(6) QS_DENSE_CASE(7) QS_DENSE_CASE(8) QS_DENSE_CASE(9) QS_DENSE_CASE(10)
+        QS_DENSE_CASE(11) QS_DENSE_CASE(12) QS_DENSE_CASE(13) QS_DENSE_CASE(14) QS_DENSE_CASE(15)
+        QS_DENSE_CASE(16) QS_DENSE_CASE(17) QS_DENSE_CASE(18) QS_DENSE_CASE(19) QS_DENSE_CASE(20)
+        QS_DENSE_CASE(21) QS_DENSE_CASE(22) QS_DENSE_CASE(23) QS_DENSE_CASE(24) QS_DENSE_CASE(25)
+        QS_DENSE_CASE(26) QS_DENSE_CASE(27) QS_DENSE_CASE(28) QS_DENSE_CASE(29) QS_DENSE_CASE(30)
+        QS_DENSE_CASE(31)
+    default:
+        break;
     }
 }
+#undef QS_DENSE_CASE
 
 // local index (within the chunk) of thread tid's register 0 in a layout:
 // thread bit j <-> local bit T[j]
@@ -106,7 +122,9 @@ __device__ __forceinline__ uint64_t local_to_phys(uint32_t l, const int *__restr
     return o;
 }
 
-// XOR swizzle of an LDS slot: bits >= 4 fold into the low nibble
+// XOR swizzle of an LDS slot (linear, bijective): local bits 4.. fold into
+// the low nibble (nibble b-4 of swlo/swhi), bit 3 folds into bits 0-2
+// (bits 28-30 of swhi).
 __device__ __forceinline__ uint32_t swz(uint32_t l, uint32_t swlo, uint32_t swhi)
 {
     uint32_t f = 0;
@@ -117,10 +135,89 @@ __device__ __forceinline__ uint32_t swz(uint32_t l, uint32_t swlo, uint32_t swhi
 #pragma unroll
     for (int b = 0; b < 2; ++b)
         if ((h >> (8 + b)) & 1u) f ^= (swhi >> (4 * b)) & 15u;
+    if ((l >> 3) & 1u) f ^= (swhi >> 28) & 7u;
     return l ^ f;
 }
 
-template <int R, typename F>
+// Barrier for LDS traffic only: wait for this wave's LDS operations, then
+// meet the other waves.  Outstanding global loads (the next chunk's prefetch)
+// and stores stay in flight.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0); vmcnt, expcnt left at their maxima
+    __builtin_amdgcn_s_barrier();
+}
+
+// Negate an amplitude when bit 31 of sb is set (sign-bit XOR, no arithmetic).
+__device__ __forceinline__ void flip(c128 &a, uint32_t sb)
+{
+    a.x = __longlong_as_double(__double_as_longlong(a.x) ^ ((unsigned long long)sb << 32));
+    a.y = __longlong_as_double(__double_as_longlong(a.y) ^ ((unsigned long long)sb << 32));
+}
+__device__ __forceinline__ void flip(c64 &a, uint32_t sb)
+{
+    a.x = __uint_as_float(__float_as_uint(a.x) ^ sb);
+    a.y = __uint_as_float(__float_as_uint(a.y) ^ sb);
+}
+
+// Register offsets from the R physical bit positions: the positions pass
+// through an empty asm so the 2^R 64-bit sums are formed next to their use
+// rather than hoisted out of the chunk loop (where they would pin registers).
+template <int R>
+__device__ __forceinline__ void reg_offsets(uint64_t (&o)[1 << R], const int (&pos)[R])
+{
+    uint64_t b[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        int p = pos[j];
+        asm volatile("" : "+s"(p));
+        b[j] = 1ull << p;
+    }
+#pragma unroll
+    for (int m = 0; m < (1 << R); ++m) {
+        uint64_t x = 0;
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+            if ((m >> j) & 1) x |= b[j];
+        o[m] = x;
+    }
+}
+
+template <int R, typename V>
+__device__ __forceinline__ void load_regs(V (&v)[1 << R], const V *__restrict__ amps, uint64_t g, const int (&pos)[R])
+{
+    uint64_t o[1 << R];
+    reg_offsets<R>(o, pos);
+#pragma unroll
+    for (int m = 0; m < (1 << R); ++m) v[m] = amps[g | o[m]];
+}
+
+template <int R, typename V>
+__device__ __forceinline__ void store_regs(const V (&v)[1 << R], V *__restrict__ amps, uint64_t g, const int (&pos)[R])
+{
+    uint64_t o[1 << R];
+    reg_offsets<R>(o, pos);
+#pragma unroll
+    for (int m = 0; m < (1 << R); ++m) amps[g | o[m]] = v[m];
+}
+
+// Chunk base: the chunk index spread over the physical qubits outside the chunk.
+__device__ __forceinline__ uint64_t chunk_base(uint64_t c, uint64_t cmask, int n)
+{
+    uint64_t base = 0;
+    int bi = 0;
+    for (int q = 0; q < n; ++q) {
+        if ((cmask >> q) & 1ull) continue;
+        if ((c >> bi) & 1ull) base |= 1ull << q;
+        ++bi;
+    }
+    return base;
+}
+
+// One workgroup per chunk: load the chunk into registers (phase 0 layout),
+// run the phases (LDS exchanges between them), store through P_out.  Several
+// workgroups share a CU, so one's HBM traffic overlaps another's arithmetic.
+template <int R, int KMAX, typename F>
 __global__ __launch_bounds__(256) void k_block(typename AmpOf<F>::type *__restrict__ amps,
                                               const int *__restrict__ prog, const F *__restrict__ mats, int n)
 {
@@ -131,198 +228,190 @@ __global__ __launch_bounds__(256) void k_block(typename AmpOf<F>::type *__restri
 
     const int nph = prog[0];
     const int C = prog[1];
+    const int flags = prog[3];
     const int tb = C - R;
     const int *__restrict__ Pin = prog + PROG_HDR;
     const int *__restrict__ Pout = prog + PROG_HDR + C;
     const uint32_t tid = threadIdx.x;
+    const int *ph0 = prog + PROG_HDR + 2 * C;
 
-    // chunk base: the workgroup index spread over the physical qubits outside the chunk
     uint64_t cmask = 0;
     for (int b = 0; b < C; ++b) cmask |= 1ull << Pin[b];
-    uint64_t base = 0;
+
+    // per-lane data of diagonal ops: staged once into LDS, after the exchange buffer
+    int *ltab = reinterpret_cast<int *>(lds_raw + ((size_t)sizeof(V) << C));
     {
-        uint64_t w = blockIdx.x;
-        int bi = 0;
-        for (int q = 0; q < n; ++q) {
-            if ((cmask >> q) & 1ull) continue;
-            if ((w >> bi) & 1ull) base |= 1ull << q;
-            ++bi;
+        const int tab_off = prog[4], tab_words = prog[5];
+        for (int i = (int)tid; i < tab_words; i += (int)blockDim.x) ltab[i] = prog[tab_off + i];
+        if (tab_words) {
+            __builtin_amdgcn_s_waitcnt(0);
+            __builtin_amdgcn_s_barrier();
         }
     }
 
-    V v[NR];
-    const int *ph = prog + PROG_HDR + 2 * C;
-    // ---- load in phase 0's layout
+    // last phase (its layout is the store layout)
+    const int *phl = ph0;
     {
-        const int *Rb = ph + PHASE_HDR;
-        const int *T = Rb + R;
-        uint64_t g = base | local_to_phys(thread_local_bits(tid, T, tb), Pin, C);
-#pragma unroll
-        for (int m = 0; m < NR; ++m) {
-            uint64_t o = 0;
-#pragma unroll
-            for (int j = 0; j < R; ++j)
-                if ((m >> j) & 1) o |= 1ull << Pin[Rb[j]];
-            v[m] = amps[g | o];
+        const int *ph = ph0;
+        for (int p = 0; p < nph; ++p) {
+            phl = ph;
+            ph = ph + PHASE_HDR + C + OP_WORDS * ph[0];
         }
     }
-    const int *prev = nullptr;
-    for (int p = 0; p < nph; ++p) {
-        const int nops = ph[0];
-        const int *Rb = ph + PHASE_HDR;
-        const int *T = Rb + R;
-        if (p > 0) {
-            // ---- exchange from the previous layout to this one through LDS
-            const uint32_t swlo = (uint32_t)ph[1], swhi = (uint32_t)ph[2];
-            const int *pR = prev + PHASE_HDR;
-            const int *pT = pR + R;
-            uint32_t wt = swz(thread_local_bits(tid, pT, tb), swlo, swhi);
-            uint32_t rt = swz(thread_local_bits(tid, T, tb), swlo, swhi);
-            __syncthreads();
+    // global offsets: per thread (VGPR); per register bit j, the physical bit of
+    // the load and store layouts (uniform) -- register offsets are rebuilt from
+    // these in every chunk instead of being kept live in 2^R 64-bit registers.
+    const uint64_t gin_t = local_to_phys(thread_local_bits(tid, ph0 + PHASE_HDR + R, tb), Pin, C);
+    const uint64_t gout_t = local_to_phys(thread_local_bits(tid, phl + PHASE_HDR + R, tb), Pout, C);
+    int bin[R], bout[R];
 #pragma unroll
-            for (int m = 0; m < NR; ++m) {
-                uint32_t lr = 0;
-#pragma unroll
-                for (int j = 0; j < R; ++j)
-                    if ((m >> j) & 1) lr |= 1u << pR[j];
-                lds[wt ^ swz(lr, swlo, swhi)] = v[m];
-            }
-            __syncthreads();
-#pragma unroll
-            for (int m = 0; m < NR; ++m) {
-                uint32_t lr = 0;
-#pragma unroll
-                for (int j = 0; j < R; ++j)
-                    if ((m >> j) & 1) lr |= 1u << Rb[j];
-                v[m] = lds[rt ^ swz(lr, swlo, swhi)];
-            }
+    for (int j = 0; j < R; ++j) {
+        bin[j] = Pin[ph0[PHASE_HDR + j]];
+        bout[j] = Pout[phl[PHASE_HDR + j]];
+    }
+    const bool hazard = (flags & 2) && nph == 1;
+
+    const uint64_t c = blockIdx.x;
+    {
+        V v[NR];
+        load_regs<R>(v, amps, chunk_base(c, cmask, n) | gin_t, bin);
+        if (hazard) {
+            // the write-back permutes positions and no exchange orders loads before
+            // stores: every wave must hold its part of the chunk before any store
+            __builtin_amdgcn_s_waitcnt(0);
+            __builtin_amdgcn_s_barrier();
         }
-        // ---- ops of this phase
-        const int *op = T + tb;
-        for (int o = 0; o < nops; ++o, op += OP_WORDS) {
-            const int w0 = op[0];
-            const int kind = w0 & 0xff;
-            const int variant = (w0 >> 8) & 0xff;
-            const int k = (w0 >> 16) & 0xff;
-            const int64_t moff = (int64_t)(uint32_t)op[1] | ((int64_t)op[2] << 32);
-            const F *__restrict__ M = mats + moff;   // moff counts scalars
-            if (kind == OP_DENSE) {
-                dense_dispatch<R, 1, F, V>(variant, v, M);
-            } else if (kind == OP_DIAG_REG) {
-                // uniform entry per register
-#pragma unroll
-                for (int m = 0; m < NR; ++m) v[m] = cmul<F, V>(M[2 * m], M[2 * m + 1], v[m]);
-            } else if (kind == OP_DIAG_ROW) {
-                // this lane's row of 2^R entries; row = the op's thread-index bits of tid
-                const uint32_t row = pext_u32(tid, (uint32_t)op[3]);
-                const F *__restrict__ E = M + (size_t)row * (2 * NR);
-#pragma unroll
-                for (int m = 0; m < NR; ++m) v[m] = cmul<F, V>(E[2 * m], E[2 * m + 1], v[m]);
-            } else if (kind == OP_SIGN_REG) {
-                const uint32_t s = (uint32_t)op[3];
-#pragma unroll
-                for (int m = 0; m < NR; ++m)
-                    if ((s >> m) & 1u) { v[m].x = -v[m].x; v[m].y = -v[m].y; }
-            } else if (kind == OP_SIGN_ROW) {
-                const uint32_t row = pext_u32(tid, (uint32_t)op[1]);
-                const uint32_t s = (uint32_t)prog[op[3] + row];
+        const int *ph = ph0;
+        const int *prev = nullptr;
+        for (int p = 0; p < nph; ++p) {
+            const int nops = ph[0];
+            const int *Rb = ph + PHASE_HDR;
+            const int *T = Rb + R;
+            if (p > 0) {
+                // ---- exchange from the previous layout to this one through LDS
+                const uint32_t swlo = (uint32_t)ph[1], swhi = (uint32_t)ph[2];
+                const int *pR = prev + PHASE_HDR;
+                const int *pT = pR + R;
+                const uint32_t wt = swz(thread_local_bits(tid, pT, tb), swlo, swhi);
+                const uint32_t rt = swz(thread_local_bits(tid, T, tb), swlo, swhi);
+                lds_barrier();      // previous readers of the buffer are done
 #pragma unroll
                 for (int m = 0; m < NR; ++m) {
-                    const F sg = ((s >> m) & 1u) ? (F)-1 : (F)1;
-                    v[m].x *= sg;
-                    v[m].y *= sg;
+                    uint32_t lr = 0;
+#pragma unroll
+                    for (int j = 0; j < R; ++j)
+                        if ((m >> j) & 1) lr |= 1u << pR[j];
+                    lds[wt ^ swz(lr, swlo, swhi)] = v[m];
                 }
-            } else {
-                // general diagonal on local bits tl[0..k-1] (ascending); entry index bit i <-> tl[i]
-                const int *tl = prog + op[3];
-                uint32_t lt = thread_local_bits(tid, T, tb);
-                uint32_t it = 0;
-                for (int i = 0; i < k; ++i) it |= ((lt >> tl[i]) & 1u) << i;
+                lds_barrier();      // every write is visible
 #pragma unroll
                 for (int m = 0; m < NR; ++m) {
                     uint32_t lr = 0;
 #pragma unroll
                     for (int j = 0; j < R; ++j)
                         if ((m >> j) & 1) lr |= 1u << Rb[j];
-                    uint32_t ir = 0;
-                    for (int i = 0; i < k; ++i) ir |= ((lr >> tl[i]) & 1u) << i;
-                    const uint32_t idx = it | ir;
-                    v[m] = cmul<F, V>(M[2 * idx], M[2 * idx + 1], v[m]);
+                    v[m] = lds[rt ^ swz(lr, swlo, swhi)];
                 }
             }
-        }
-        prev = ph;
-        ph = op;
-        // skip past nothing: op now points after the last op of this phase
-    }
-    // ---- store in the last layout, through P_out
-    if ((prog[3] & 2) && nph == 1) {
-        // No exchange (hence no barrier) separated the loads from the stores, and the
-        // write-back permutes positions: a store may target an amplitude another wave
-        // has not loaded yet.  Wait for this wave's loads, then for every wave.
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-    }
-    {
-        const int *Rb = prev + PHASE_HDR;
-        const int *T = Rb + R;
-        uint64_t g = base | local_to_phys(thread_local_bits(tid, T, tb), Pout, C);
+            // ---- ops of this phase
+            const int *op = T + tb;
+            for (int o = 0; o < nops; ++o, op += OP_WORDS) {
+                const int w0 = op[0];
+                const int kind = w0 & 0xff;
+                const int variant = (w0 >> 8) & 0xff;
+                const int k = (w0 >> 16) & 0xff;
+                const int64_t moff = (int64_t)(uint32_t)op[1] | ((int64_t)op[2] << 32);
+                const F *__restrict__ M = mats + moff;   // moff counts scalars
+                if (kind == OP_DENSE) {
+                    dense_dispatch<R, KMAX, F, V>(variant, v, M);
+                } else if (kind == OP_SIGN_ROW) {
+                    const uint32_t row = pext_u32(tid, (uint32_t)op[1]);
+                    const uint32_t s = (uint32_t)ltab[op[3] + row];
 #pragma unroll
-        for (int m = 0; m < NR; ++m) {
-            uint64_t o = 0;
+                    for (int m = 0; m < NR; ++m) flip(v[m], (s << (31 - m)) & 0x80000000u);
+                } else if (kind == OP_SIGN_REG) {
+                    const uint32_t s = (uint32_t)op[3];
 #pragma unroll
-            for (int j = 0; j < R; ++j)
-                if ((m >> j) & 1) o |= 1ull << Pout[Rb[j]];
-            amps[g | o] = v[m];
+                    for (int m = 0; m < NR; ++m) flip(v[m], (s << (31 - m)) & 0x80000000u);
+                } else if (kind == OP_DIAG_REG) {
+#pragma unroll
+                    for (int m = 0; m < NR; ++m) v[m] = cmul<F, V>(M[2 * m], M[2 * m + 1], v[m]);
+                } else {   // OP_DIAG_ROW: this lane's row of the op's table in LDS
+                    const uint32_t row = pext_u32(tid, (uint32_t)op[1]);
+                    const V *E = reinterpret_cast<const V *>(ltab + op[3]) + (size_t)row * NR;
+#pragma unroll
+                    for (int m = 0; m < NR; ++m) {
+                        const V e = E[m];
+                        v[m] = cmul<F, V>(e.x, e.y, v[m]);
+                        // keep at most four table reads in flight (register pressure)
+                        if ((m & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+                    }
+                }
+            }
+            prev = ph;
+            ph = op;
         }
+        // ---- store in the last layout, through P_out
+        store_regs<R>(v, amps, chunk_base(c, cmask, n) | gout_t, bout);
     }
 }
 
-template <int R, typename F>
-hipError_t launch_R(qs_state *st, const int *d_prog, const F *d_mats, int C)
+template <int R, int KMAX, typename F>
+hipError_t launch_RK(qs_state *st, const int *d_prog, const F *d_mats, int C, size_t tab_bytes)
 {
     using V = typename AmpOf<F>::type;
-    size_t lds = ((size_t)1 << C) * sizeof(V);
-    auto kern = k_block<R, F>;
+    const size_t lds = ((size_t)1 << C) * sizeof(V) + ((tab_bytes + 15) & ~(size_t)15);
+    if (lds > 160u * 1024u) return hipErrorInvalidValue;
+    auto kern = k_block<R, KMAX, F>;
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    unsigned threads = 1u << (C - R);
-    uint64_t grid = 1ull << (st->n - C);
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(threads), lds, st->stream,
+    const unsigned threads = 1u << (C - R);
+    const uint64_t nchunks = 1ull << (st->n - C);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nchunks), dim3(threads), lds, st->stream,
                        reinterpret_cast<V *>(st->amps), d_prog, d_mats, st->n);
     return hipGetLastError();
 }
 
+template <int R, typename F>
+hipError_t launch_R(qs_state *st, const int *d_prog, const F *d_mats, int C, size_t tab, int kmax)
+{
+    if (kmax <= 2 || R <= 2) return launch_RK<R, (R < 2 ? R : 2), F>(st, d_prog, d_mats, C, tab);
+    return launch_RK<R, R, F>(st, d_prog, d_mats, C, tab);
+}
+
 template <typename F>
-hipError_t launch_F(qs_state *st, int r, const int *d_prog, const F *d_mats, int C)
+hipError_t launch_F(qs_state *st, int r, const int *d_prog, const F *d_mats, int C, size_t tab, int kmax)
 {
     switch (r) {
-    case 1: return launch_R<1, F>(st, d_prog, d_mats, C);
-    case 2: return launch_R<2, F>(st, d_prog, d_mats, C);
-    case 3: return launch_R<3, F>(st, d_prog, d_mats, C);
-    case 4: return launch_R<4, F>(st, d_prog, d_mats, C);
-    case 5: return launch_R<5, F>(st, d_prog, d_mats, C);
+    case 1: return launch_R<1, F>(st, d_prog, d_mats, C, tab, kmax);
+    case 2: return launch_R<2, F>(st, d_prog, d_mats, C, tab, kmax);
+    case 3: return launch_R<3, F>(st, d_prog, d_mats, C, tab, kmax);
+    case 4: return launch_R<4, F>(st, d_prog, d_mats, C, tab, kmax);
+    case 5: return launch_R<5, F>(st, d_prog, d_mats, C, tab, kmax);
     default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-hipError_t launch_block_prog(qs_state *st, int r, int C, const int *d_prog, const void *d_mats)
+hipError_t launch_block_prog(qs_state *st, int r, int C, const int *d_prog, const void *d_mats, size_t tab_bytes,
+                             int kmax_dense)
 {
     if (C - r > 8 || C < r || st->n < C) return hipErrorInvalidValue;
-    if (st->dtype == QS_C64) return launch_F<float>(st, r, d_prog, reinterpret_cast<const float *>(d_mats), C);
-    return launch_F<double>(st, r, d_prog, reinterpret_cast<const double *>(d_mats), C);
+    if (st->dtype == QS_C64)
+        return launch_F<float>(st, r, d_prog, reinterpret_cast<const float *>(d_mats), C, tab_bytes, kmax_dense);
+    return launch_F<double>(st, r, d_prog, reinterpret_cast<const double *>(d_mats), C, tab_bytes, kmax_dense);
 }
 
 hipError_t launch_block(qs_state *st, const Plan &p, int b)
 {
     const int *prog = reinterpret_cast<const int *>(p.d_prog) + p.prog_off[b];
-    return launch_block_prog(st, p.r, p.C, prog, p.d_mats);
+    const size_t tab_bytes = (size_t)p.h_prog[p.prog_off[b] + 5] * 4;
+    return launch_block_prog(st, p.r, p.C, prog, p.d_mats, tab_bytes, p.block_kmax[b]);
 }
 
 }  // namespace qs

@@ -556,9 +556,10 @@ qs_status build_plan(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan 
     if (C < 1 || C > kMaxChunk) { *err = "qs_fuse: chunk_qubits must be 1..14"; return QS_EINVAL; }
     int L = opts.low_qubits ? opts.low_qubits : 4;
     C = std::min(C, n);
+    r = std::max(r, C - 8);                    // at most 256 threads per workgroup
+    if (r > kMaxReg) { *err = "qs_fuse: chunk_qubits must be <= 13 (256 threads x 32 registers)"; return QS_EINVAL; }
     r = std::min(r, C);
     if (maxk > r) { *err = "qs_fuse: a gate is wider than the chunk"; return QS_EINVAL; }
-    if (C - r > 10) { *err = "qs_fuse: chunk_qubits - reg_qubits must be <= 10 (1024 threads)"; return QS_EINVAL; }
     L = std::min(L, C - r);                    // low qubits live in thread bits of load/store layouts
     if (L < 0) L = 0;
     p->C = C; p->r = r; p->L = L;
@@ -830,8 +831,9 @@ qs_status build_plan(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan 
 // Encoding for the blocked kernel
 // ---------------------------------------------------------------------------
 namespace {
-// Low-nibble images of local bits under swizzle nibbles F.
-uint32_t img(int b, const uint32_t *F) { return b < 4 ? (1u << b) : F[b - 4]; }
+// Low-nibble images of local bits under the swizzle: bits 0-2 map to
+// themselves, bit 3 to 8 ^ g3 (g3 in bits 0-2), bit b >= 4 to F[b-4].
+uint32_t img(int b, const uint32_t *F, uint32_t g3) { return b < 3 ? (1u << b) : b == 3 ? (8u | g3) : F[b - 4]; }
 
 bool independent4(uint32_t a, uint32_t b, uint32_t c, uint32_t d)
 {
@@ -848,25 +850,47 @@ bool independent4(uint32_t a, uint32_t b, uint32_t c, uint32_t d)
     return true;
 }
 
+bool independent3(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t v[3] = {a, b, c};
+    uint32_t seen = 0;
+    for (int s = 0; s < 8; ++s) {
+        uint32_t x = 0;
+        for (int i = 0; i < 3; ++i)
+            if (s >> i & 1) x ^= v[i];
+        if (seen >> x & 1) return false;
+        seen |= 1u << x;
+    }
+    return true;
+}
+
 uint64_t choose_swizzle(const Layout &from, const Layout &to, int C, int r)
 {
     int tb = C - r;
     if (tb < 4 || C <= 4) return 0;
     uint32_t F[16] = {0};
+    uint32_t g3 = 0;
     uint64_t rng = 0x9E3779B97F4A7C15ull ^ (uint64_t)(from.T[0] * 131 + to.T[0] * 17 + C);
     auto next = [&]() { rng ^= rng << 13; rng ^= rng >> 7; rng ^= rng << 17; return rng; };
     bool inset[32] = {false};
     for (int i = 0; i < 4; ++i) { inset[from.T[i]] = true; inset[to.T[i]] = true; }
-    for (int tries = 0; tries < 4000; ++tries) {
-        bool ok1 = independent4(img(from.T[0], F), img(from.T[1], F), img(from.T[2], F), img(from.T[3], F));
-        bool ok2 = independent4(img(to.T[0], F), img(to.T[1], F), img(to.T[2], F), img(to.T[3], F));
-        if (ok1 && ok2) break;
+    // lanes 0-15 of a wavefront must hit 16 distinct 16-byte slots (mod 256 B), and
+    // lanes 0-7 8 distinct slots (mod 128 B), on both sides of the exchange
+    auto good = [&](const Layout &L) {
+        return independent4(img(L.T[0], F, g3), img(L.T[1], F, g3), img(L.T[2], F, g3), img(L.T[3], F, g3)) &&
+               independent3(img(L.T[0], F, g3) & 7, img(L.T[1], F, g3) & 7, img(L.T[2], F, g3) & 7);
+    };
+    for (int tries = 0; tries < 20000; ++tries) {
+        if (good(from) && good(to)) break;
         for (int b = 4; b < C; ++b) F[b - 4] = inset[b] ? (uint32_t)(next() & 15) : 0;
+        g3 = inset[3] ? (uint32_t)(next() & 7) : 0;
     }
     uint64_t w = 0;
     for (int b = 4; b < C; ++b) w |= (uint64_t)(F[b - 4] & 15) << (4 * (b - 4));
+    w |= (uint64_t)(g3 & 7) << 60;      // nibble 15: fold of bit 3 into bits 0-2
     return w;
 }
+
 }  // namespace
 
 void encode_plan(Plan *p)
@@ -874,10 +898,16 @@ void encode_plan(Plan *p)
     p->h_prog.clear();
     p->h_mats.clear();
     p->prog_off.clear();
+    p->block_kmax.clear();
     const int C = p->C, r = p->r;
     for (const Block &blk : p->blocks) {
         int64_t start = (int64_t)p->h_prog.size();
         p->prog_off.push_back(start);
+        int bk = 0;
+        for (const Phase &P : blk.phases)
+            for (const Op &op : P.ops)
+                if (op.kind == OP_DENSE) bk = std::max(bk, op.k);
+        p->block_kmax.push_back(bk);
         std::vector<int32_t> w;
         w.push_back((int32_t)blk.phases.size());
         w.push_back(C);
@@ -886,9 +916,14 @@ void encode_plan(Plan *p)
         // threads' load positions (P_out != P_in), so loads must all complete
         // before any store even when no exchange separates them
         w.push_back((blk.permute_only ? 1 : 0) | (blk.P_out != blk.P_in ? 2 : 0));
+        w.push_back(0);   // table offset, patched below
+        w.push_back(0);   // table words
+        w.push_back(0);
+        w.push_back(0);
         for (int b = 0; b < C; ++b) w.push_back(blk.P_in[b]);
         for (int b = 0; b < C; ++b) w.push_back(blk.P_out[b]);
-        std::vector<std::pair<size_t, std::vector<int32_t>>> tail_fix;   // (word index to patch, words to append)
+        std::vector<int32_t> tab;   // per-lane data of diagonal ops, staged in LDS by the kernel
+        const bool c64 = (p->dtype == QS_C64);
         for (size_t ph = 0; ph < blk.phases.size(); ++ph) {
             const Phase &P = blk.phases[ph];
             uint64_t swz = (ph > 0) ? choose_swizzle(blk.phases[ph - 1].lay, P.lay, C, r) : 0;
@@ -946,27 +981,50 @@ void encode_plan(Plan *p)
                         w.push_back(OP_SIGN_ROW | (op.k << 16));
                         w.push_back((int32_t)tmask);
                         w.push_back(0);
-                        w.push_back(0);
-                        tail_fix.push_back({w.size() - 1, masks});
+                        w.push_back((int32_t)tab.size());
+                        tab.insert(tab.end(), masks.begin(), masks.end());
                     }
                     continue;
                 }
-                for (int row = 0; row < rows; ++row)
+                if (kt == 0) {
                     for (int m = 0; m < NR; ++m) {
-                        cplx z = entry(row, m);
+                        cplx z = entry(0, m);
                         p->h_mats.push_back(z.real());
                         p->h_mats.push_back(z.imag());
                     }
-                w.push_back((kt == 0 ? OP_DIAG_REG : OP_DIAG_ROW) | (op.k << 16));
-                w.push_back((int32_t)(uint32_t)(moff & 0xffffffff));
-                w.push_back((int32_t)(uint32_t)(moff >> 32));
+                    w.push_back(OP_DIAG_REG | (op.k << 16));
+                    w.push_back((int32_t)(uint32_t)(moff & 0xffffffff));
+                    w.push_back((int32_t)(uint32_t)(moff >> 32));
+                    w.push_back(0);
+                    continue;
+                }
+                while (tab.size() % 4) tab.push_back(0);     // 16-byte aligned rows
+                w.push_back(OP_DIAG_ROW | (op.k << 16));
                 w.push_back((int32_t)tmask);
+                w.push_back(0);
+                w.push_back((int32_t)tab.size());
+                for (int row = 0; row < rows; ++row)
+                    for (int m = 0; m < NR; ++m) {
+                        cplx z = entry(row, m);
+                        if (c64) {
+                            float f[2] = {(float)z.real(), (float)z.imag()};
+                            int32_t u[2];
+                            std::memcpy(u, f, 8);
+                            tab.push_back(u[0]);
+                            tab.push_back(u[1]);
+                        } else {
+                            double d[2] = {z.real(), z.imag()};
+                            int32_t u[4];
+                            std::memcpy(u, d, 16);
+                            tab.insert(tab.end(), u, u + 4);
+                        }
+                    }
             }
         }
-        for (auto &tf : tail_fix) {
-            w[tf.first] = (int32_t)w.size();
-            for (int32_t x : tf.second) w.push_back(x);
-        }
+        while (w.size() % 4) w.push_back(0);
+        w[4] = (int32_t)w.size();
+        w[5] = (int32_t)tab.size();
+        w.insert(w.end(), tab.begin(), tab.end());
         p->h_prog.insert(p->h_prog.end(), w.begin(), w.end());
     }
     if (p->dtype == QS_C64) {

@@ -82,6 +82,7 @@ struct Plan {
     void *d_prog = nullptr;             // int32 program words for all blocks
     void *d_mats = nullptr;             // matrices (FP64 or FP32 by dtype)
     std::vector<int64_t> prog_off;      // per block: offset of its program in d_prog (int32 words)
+    std::vector<int> block_kmax;        // per block: widest dense op (selects the kernel variant)
     std::vector<int32_t> h_prog;
     std::vector<double> h_mats;
     std::vector<float> h_mats32;
@@ -101,8 +102,9 @@ void block_features(const Plan &p, std::vector<float> *out);
 // ---------------------------------------------------------------------------
 // Program encoding read by the blocked kernel (int32 words per block):
 //   [0] nphases, [1] C, [2] r, [3] flags (bit 0 swap pass, bit 1 P_out != P_in)
-//   [4 .. 4+C)        P_in
-//   [4+C .. 4+2C)     P_out
+//   [4] table offset (words from block start, multiple of 4), [5] table words, [6..8) 0
+//   [8 .. 8+C)        P_in
+//   [8+C .. 8+2C)     P_out
 //   then per phase:
 //     [0] nops, [1] swz_lo (F nibbles for high bits 0..7), [2] swz_hi (8..15), [3] reserved
 //     [4 .. 4+r)      R
@@ -110,13 +112,16 @@ void block_features(const Plan &p, std::vector<float> *out);
 //     then per op: 4 words: [kind | (variant << 8) | (k << 16)] [w1] [w2] [w3]
 //       DENSE   : variant = register mask; w1,w2 = matrix offset (scalars, lo/hi)
 //       DIAG_REG: w1,w2 = offset of 2^r entries (register order)
-//       DIAG_ROW: w1,w2 = offset of 2^kt * 2^r entries; w3 = tmask (thread-index bits of the row)
+//       DIAG_ROW: w1 = tmask (thread-index bits of the row); w3 = word offset in the table of
+//                 2^kt rows of 2^r entries (complex128: 4 words each, complex64: 2)
 //       SIGN_REG: w3 = mask over registers (bit m set: negate register m)
-//       SIGN_ROW: w1 = tmask; w3 = word offset (from block start) of 2^kt row masks
+//       SIGN_ROW: w1 = tmask; w3 = word offset in the table of 2^kt row masks
+// The table (per-lane data of diagonal ops) is copied into LDS, after the
+// exchange buffer, once per workgroup.
 // The swizzle for the exchange INTO a phase: slot(l) = l ^ F(l >> 4) where
 // F XORs nibble b of swz (bits 4b..4b+3) for every set bit b of (l >> 4).
 // ---------------------------------------------------------------------------
-enum { PROG_HDR = 4, PHASE_HDR = 4, OP_WORDS = 4 };
+enum { PROG_HDR = 8, PHASE_HDR = 4, OP_WORDS = 4 };
 
 }  // namespace qs
 
@@ -153,5 +158,6 @@ hipError_t launch_probs(qs_state *st, double *out);
 hipError_t launch_expect(qs_state *st, int nterms, const qs_pauli *terms, double *partials, int nparts);
 int expect_partials(int n);
 hipError_t launch_block(qs_state *st, const Plan &p, int b);
-hipError_t launch_block_prog(qs_state *st, int r, int C, const int *d_prog, const void *d_mats);
+hipError_t launch_block_prog(qs_state *st, int r, int C, const int *d_prog, const void *d_mats, size_t tab_bytes,
+                             int kmax_dense);
 }

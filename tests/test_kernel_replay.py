@@ -17,7 +17,7 @@ from oracle import sim
 from paper_2406_14084_amd import inputs as I
 from paper_2406_14084_amd import qs
 
-PROG_HDR, PHASE_HDR, OP_WORDS = 4, 4, 4
+PROG_HDR, PHASE_HDR, OP_WORDS = 8, 4, 4
 
 
 def _pdep(v, mask):
@@ -60,6 +60,7 @@ def _swz(l, swlo, swhi):
         f ^= np.where((h >> b) & 1, (swlo >> (4 * b)) & 15, 0)
     for b in range(2):
         f ^= np.where((h >> (8 + b)) & 1, (swhi >> (4 * b)) & 15, 0)
+    f ^= np.where((l >> 3) & 1, (swhi >> 28) & 7, 0)
     return l ^ f
 
 
@@ -79,6 +80,10 @@ def replay_block(psi, w, n, R, mats):
         base |= ((wg >> bi) & 1) << q
     tid = np.arange(1 << tb, dtype=np.int64)
     ph = PROG_HDR + 2 * C
+    tab_off, tab_words = int(w[4]), int(w[5])
+    assert tab_off % 4 == 0 and (tab_words == 0 or tab_off >= ph)
+    # the table plus the exchange buffer must fit the 160 KiB of LDS
+    assert (16 << C) + 4 * tab_words <= 160 * 1024
 
     def layout(at):
         Rb = [int(x) for x in w[at + PHASE_HDR:at + PHASE_HDR + R]]
@@ -138,38 +143,30 @@ def replay_block(psi, w, n, R, mats):
             elif kind == 2:       # register diagonal: uniform entry per register
                 E = mats[moff:moff + 2 * NR].view(np.complex128)
                 v = v * E[None, None, :]
-            elif kind == 3:       # per-row diagonal: row = pext(tid, tmask)
-                tmask = int(w[op + 3])
+            elif kind == 3:       # per-row diagonal from the LDS table: row = pext(tid, tmask)
+                tmask = int(w[op + 1])
                 row = _pext(tid, tmask)
                 kt = bin(tmask).count("1")
-                E = mats[moff:moff + 2 * NR * (1 << kt)].view(np.complex128).reshape(1 << kt, NR)
+                a = tab_off + int(w[op + 3])
+                assert a % 4 == 0 and int(w[op + 3]) + 4 * NR * (1 << kt) <= tab_words
+                E = np.ascontiguousarray(w[a:a + 4 * NR * (1 << kt)]).view(np.complex128).reshape(1 << kt, NR)
                 v = v * E[row][None, :, :]
             elif kind == 4:       # +-1 on registers
                 s = int(np.uint32(w[op + 3]))
                 sg = np.array([-1.0 if (s >> m) & 1 else 1.0 for m in range(NR)])
                 v = v * sg[None, None, :]
-            elif kind == 5:       # +-1 per row
+            elif kind == 5:       # +-1 per row, masks in the LDS table
                 tmask = int(w[op + 1])
                 row = _pext(tid, tmask)
                 kt = bin(tmask).count("1")
-                a = int(w[op + 3])
+                a = tab_off + int(w[op + 3])
+                assert int(w[op + 3]) + (1 << kt) <= tab_words
                 masks = np.array([int(np.uint32(x)) for x in w[a:a + (1 << kt)]], dtype=np.int64)
                 s = masks[row]
                 sg = np.where(((s[:, None] >> np.arange(NR)[None, :]) & 1) == 1, -1.0, 1.0)
                 v = v * sg[None, :, :]
             else:
-                a = int(w[op + 3])
-                tl = [int(x) for x in w[a:a + k]]
-                D = 1 << k
-                Dg = mats[moff:moff + 2 * D].view(np.complex128)
-                lt = _thread_local(tid, T, tb)
-                it = np.zeros_like(lt)
-                for i, b in enumerate(tl):
-                    it |= ((lt >> b) & 1) << i
-                for m in range(NR):
-                    lr = sum(1 << Rb[j] for j in range(R) if (m >> j) & 1)
-                    ir = sum(((lr >> b) & 1) << i for i, b in enumerate(tl))
-                    v[:, :, m] = v[:, :, m] * Dg[(it | ir)][None, :]
+                raise AssertionError("unknown op kind %d" % kind)
             op += OP_WORDS
         prev = ph
         ph = op
@@ -280,3 +277,29 @@ def _op_kinds(p):
                     kinds.add(int(w[op]) & 0xff); op += OP_WORDS
                 ph = op
     return kinds
+
+
+def test_exchange_swizzle_spreads_lanes():
+    """For every exchange of the 30-qubit benchmark plan, lanes 0-7 of a
+    wavefront hit 8 distinct 16-byte LDS slots mod 128 B and lanes 0-15 hit 16
+    distinct slots mod 256 B, on both the write and the read side."""
+    c = I.random_u3_2q(n=30, depth=40, seed=30002)
+    p = qs.Plan(c, kmax=5)
+    w, offs, R, C, mats = p.program()
+    lanes = np.arange(64, dtype=np.int64)
+    bad = 0
+    total = 0
+    for o in offs:
+        nph = int(w[o]); ph = o + PROG_HDR + 2 * C; pT = None
+        for i in range(nph):
+            T = [int(x) for x in w[ph + PHASE_HDR + R:ph + PHASE_HDR + C]]
+            if i > 0:
+                swlo, swhi = int(np.uint32(w[ph + 1])), int(np.uint32(w[ph + 2]))
+                for TT in (pT, T):
+                    s = _swz(_thread_local(lanes, TT, C - R), swlo, swhi)
+                    total += 1
+                    if len(set((s[:8] & 7).tolist())) < 8 or len(set((s[:16] & 15).tolist())) < 16:
+                        bad += 1
+            pT = T
+            ph = ph + PHASE_HDR + C + OP_WORDS * int(w[ph])
+    assert total > 0 and bad == 0, (bad, total)
