@@ -47,8 +47,8 @@ __device__ __forceinline__ constexpr int pdep_c(int v)
 // the MASK bits clear, the 2^K amplitudes base | pdep(c) are multiplied by the
 // 2^K x 2^K matrix M (row-major, interleaved re/im, index bit i <-> i-th set
 // bit of MASK).
-template <int R, int MASK, typename F, typename V>
-__device__ __forceinline__ void apply_dense(V (&v)[1 << R], const F *__restrict__ M)
+template <int R, int MASK, typename F, typename V, typename P>
+__device__ __forceinline__ void apply_dense(V (&v)[1 << R], P M)
 {
     constexpr int D = MaskInfo<MASK>::D;
 #pragma unroll
@@ -74,11 +74,11 @@ __device__ __forceinline__ void apply_dense(V (&v)[1 << R], const F *__restrict_
 #define QS_DENSE_CASE(MM)                                                                 \
     case MM:                                                                              \
         if constexpr ((MM) < (1 << R) && __builtin_popcount(MM) <= KMAX)                  \
-            apply_dense<R, ((MM) < (1 << R) ? (MM) : 1), F, V>(v, M);                      \
+            apply_dense<R, ((MM) < (1 << R) ? (MM) : 1), F, V, P>(v, M);                   \
         break;
 
-template <int R, int KMAX, typename F, typename V>
-__device__ __forceinline__ void dense_dispatch(int mask, V (&v)[1 << R], const F *__restrict__ M)
+template <int R, int KMAX, typename F, typename V, typename P>
+__device__ __forceinline__ void dense_dispatch(int mask, V (&v)[1 << R], P M)
 {
     switch (mask) {
         QS_DENSE_CASE(1) QS_DENSE_CASE(2) QS_DENSE_CASE(3) QS_DENSE_CASE(4) QS_DENSE_CASE(5)
@@ -222,8 +222,8 @@ __global__ __launch_bounds__(256) void k_block(typename AmpOf<F>::type *__restri
                                               const int *__restrict__ prog, const F *__restrict__ mats, int n)
 {
     using V = typename AmpOf<F>::type;
+    using CF = __attribute__((address_space(4))) F;
     extern __shared__ unsigned char lds_raw[];
-    V *lds = reinterpret_cast<V *>(lds_raw);
     constexpr int NR = 1 << R;
 
     const int nph = prog[0];
@@ -255,7 +255,7 @@ __global__ __launch_bounds__(256) void k_block(typename AmpOf<F>::type *__restri
         const int *ph = ph0;
         for (int p = 0; p < nph; ++p) {
             phl = ph;
-            ph = ph + PHASE_HDR + C + OP_WORDS * ph[0];
+            ph = ph + PHASE_HDR + C + 2 * tb + 2 * NR + OP_WORDS * ph[0];
         }
     }
     // global offsets: per thread (VGPR); per register bit j, the physical bit of
@@ -287,43 +287,39 @@ __global__ __launch_bounds__(256) void k_block(typename AmpOf<F>::type *__restri
             const int nops = ph[0];
             const int *Rb = ph + PHASE_HDR;
             const int *T = Rb + R;
+            const int *X = T + tb;                 // exchange block of this phase
             if (p > 0) {
                 // ---- exchange from the previous layout to this one through LDS
-                const uint32_t swlo = (uint32_t)ph[1], swhi = (uint32_t)ph[2];
-                const int *pR = prev + PHASE_HDR;
-                const int *pT = pR + R;
-                const uint32_t wt = swz(thread_local_bits(tid, pT, tb), swlo, swhi);
-                const uint32_t rt = swz(thread_local_bits(tid, T, tb), swlo, swhi);
+                uint32_t wt = 0, rt = 0;
+                for (int j = 0; j < tb; ++j)
+                    if ((tid >> j) & 1u) {
+                        wt ^= (uint32_t)X[j];
+                        rt ^= (uint32_t)X[tb + j];
+                    }
+                const int *wo = X + 2 * tb;
+                const int *ro = wo + NR;
                 lds_barrier();      // previous readers of the buffer are done
 #pragma unroll
-                for (int m = 0; m < NR; ++m) {
-                    uint32_t lr = 0;
-#pragma unroll
-                    for (int j = 0; j < R; ++j)
-                        if ((m >> j) & 1) lr |= 1u << pR[j];
-                    lds[wt ^ swz(lr, swlo, swhi)] = v[m];
-                }
+                for (int m = 0; m < NR; ++m) *reinterpret_cast<V *>(lds_raw + (wt ^ (uint32_t)wo[m])) = v[m];
                 lds_barrier();      // every write is visible
 #pragma unroll
-                for (int m = 0; m < NR; ++m) {
-                    uint32_t lr = 0;
-#pragma unroll
-                    for (int j = 0; j < R; ++j)
-                        if ((m >> j) & 1) lr |= 1u << Rb[j];
-                    v[m] = lds[rt ^ swz(lr, swlo, swhi)];
-                }
+                for (int m = 0; m < NR; ++m) v[m] = *reinterpret_cast<const V *>(lds_raw + (rt ^ (uint32_t)ro[m]));
             }
             // ---- ops of this phase
-            const int *op = T + tb;
+            const int *op = X + 2 * tb + 2 * NR;
             for (int o = 0; o < nops; ++o, op += OP_WORDS) {
                 const int w0 = op[0];
                 const int kind = w0 & 0xff;
                 const int variant = (w0 >> 8) & 0xff;
                 const int k = (w0 >> 16) & 0xff;
-                const int64_t moff = (int64_t)(uint32_t)op[1] | ((int64_t)op[2] << 32);
-                const F *__restrict__ M = mats + moff;   // moff counts scalars
+                // uniform across the workgroup: keep the coefficient address scalar
+                const uint32_t mlo = __builtin_amdgcn_readfirstlane((uint32_t)op[1]);
+                const uint32_t mhi = __builtin_amdgcn_readfirstlane((uint32_t)op[2]);
+                // read through the constant address space: uniform loads of coefficients
+                // become scalar (SMEM) loads instead of per-lane vector loads
+                const CF *M = (const CF *)(uintptr_t)(mats + ((int64_t)mlo | ((int64_t)mhi << 32)));
                 if (kind == OP_DENSE) {
-                    dense_dispatch<R, KMAX, F, V>(variant, v, M);
+                    dense_dispatch<R, KMAX, F, V, const CF *>(variant, v, M);
                 } else if (kind == OP_SIGN_ROW) {
                     const uint32_t row = pext_u32(tid, (uint32_t)op[1]);
                     const uint32_t s = (uint32_t)ltab[op[3] + row];

@@ -934,6 +934,38 @@ void encode_plan(Plan *p)
             for (int j = 0; j < r; ++j) w.push_back(P.lay.R[j]);
             for (int j = 0; j < C - r; ++j) w.push_back(P.lay.T[j]);
             const int NR = 1 << r;
+            const int amp_bytes = (p->dtype == QS_C64) ? 8 : 16;
+            {
+                // exchange block: the swizzle is XOR-linear, so every slot splits into
+                // per-thread-bit and per-register contributions, precomputed here
+                const uint32_t swlo = (uint32_t)(swz & 0xffffffffu), swhi = (uint32_t)(swz >> 32);
+                auto sw = [&](uint32_t l) {
+                    uint32_t f = 0, hh = l >> 4;
+                    for (int b = 0; b < 8; ++b)
+                        if (hh >> b & 1) f ^= (swlo >> (4 * b)) & 15u;
+                    for (int b = 0; b < 2; ++b)
+                        if (hh >> (8 + b) & 1) f ^= (swhi >> (4 * b)) & 15u;
+                    if (l >> 3 & 1) f ^= (swhi >> 28) & 7u;
+                    return l ^ f;
+                };
+                const bool has = ph > 0;
+                const Layout *pl = has ? &blk.phases[ph - 1].lay : nullptr;
+                for (int j = 0; j < C - r; ++j) w.push_back(has ? (int32_t)(sw(1u << pl->T[j]) * amp_bytes) : 0);
+                for (int j = 0; j < C - r; ++j) w.push_back(has ? (int32_t)(sw(1u << P.lay.T[j]) * amp_bytes) : 0);
+                for (int m = 0; m < NR; ++m) {
+                    uint32_t lr = 0;
+                    if (has)
+                        for (int j = 0; j < r; ++j)
+                            if (m >> j & 1) lr |= 1u << pl->R[j];
+                    w.push_back(has ? (int32_t)(sw(lr) * amp_bytes) : 0);
+                }
+                for (int m = 0; m < NR; ++m) {
+                    uint32_t lr = 0;
+                    for (int j = 0; j < r; ++j)
+                        if (m >> j & 1) lr |= 1u << P.lay.R[j];
+                    w.push_back(has ? (int32_t)(sw(lr) * amp_bytes) : 0);
+                }
+            }
             for (const Op &op : P.ops) {
                 int64_t moff = (int64_t)p->h_mats.size();
                 if (op.kind == OP_DENSE) {

@@ -109,6 +109,11 @@ void block_features(const Plan &p, std::vector<float> *out);
 //     [0] nops, [1] swz_lo (F nibbles for high bits 0..7), [2] swz_hi (8..15), [3] reserved
 //     [4 .. 4+r)      R
 //     [4+r .. 4+C)    T
+//     exchange into this phase (zeros for phase 0), LDS byte offsets:
+//       tb words: write-side contribution of thread bit j (previous layout)
+//       tb words: read-side contribution of thread bit j (this layout)
+//       2^r words: write-side offset of register m; 2^r words: read-side offset of register m
+//       (slot of (thread, m) = XOR of the thread's bit contributions ^ offset of m)
 //     then per op: 4 words: [kind | (variant << 8) | (k << 16)] [w1] [w2] [w3]
 //       DENSE   : variant = register mask; w1,w2 = matrix offset (scalars, lo/hi)
 //       DIAG_REG: w1,w2 = offset of 2^r entries (register order)

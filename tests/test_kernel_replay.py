@@ -116,13 +116,27 @@ def replay_block(psi, w, n, R, mats):
                            for m in range(NR)])
             ws = wt[:, None] ^ wl[None, :]
             rs = rt[:, None] ^ rl[None, :]
+            # the kernel forms the same slots from the program's exchange block
+            X = ph + PHASE_HDR + C
+            ab = 16
+            xw = [int(x) for x in w[X:X + tb]]
+            xr = [int(x) for x in w[X + tb:X + 2 * tb]]
+            wo = np.array([int(x) for x in w[X + 2 * tb:X + 2 * tb + NR]])
+            ro = np.array([int(x) for x in w[X + 2 * tb + NR:X + 2 * tb + 2 * NR]])
+            kw = np.zeros_like(tid)
+            kr = np.zeros_like(tid)
+            for j in range(tb):
+                kw ^= np.where((tid >> j) & 1, xw[j], 0)
+                kr ^= np.where((tid >> j) & 1, xr[j], 0)
+            assert np.array_equal(kw[:, None] ^ wo[None, :], ws * ab)
+            assert np.array_equal(kr[:, None] ^ ro[None, :], rs * ab)
             for s in (ws, rs):
                 assert s.min() >= 0 and s.max() < (1 << C)
                 assert np.unique(s).size == s.size == (1 << C), "exchange is not a bijection"
             lds = np.zeros((nwg, 1 << C), dtype=np.complex128)
             lds[:, ws.reshape(-1)] = v.reshape(nwg, -1)
             v = lds[:, rs.reshape(-1)].reshape(nwg, 1 << tb, NR)
-        op = ph + PHASE_HDR + C
+        op = ph + PHASE_HDR + C + 2 * tb + 2 * NR
         for _ in range(nops):
             w0 = int(w[op])
             kind, variant, k = w0 & 0xff, (w0 >> 8) & 0xff, (w0 >> 16) & 0xff
@@ -272,7 +286,7 @@ def _op_kinds(p):
     for o in offs:
             nph = int(w[o]); ph = o + PROG_HDR + 2 * C
             for _ in range(nph):
-                nops = int(w[ph]); op = ph + PHASE_HDR + C
+                nops = int(w[ph]); op = ph + PHASE_HDR + C + 2 * (C - R) + 2 * (1 << R)
                 for _ in range(nops):
                     kinds.add(int(w[op]) & 0xff); op += OP_WORDS
                 ph = op
@@ -301,5 +315,5 @@ def test_exchange_swizzle_spreads_lanes():
                     if len(set((s[:8] & 7).tolist())) < 8 or len(set((s[:16] & 15).tolist())) < 16:
                         bad += 1
             pT = T
-            ph = ph + PHASE_HDR + C + OP_WORDS * int(w[ph])
+            ph = ph + PHASE_HDR + C + 2 * (C - R) + 2 * (1 << R) + OP_WORDS * int(w[ph])
     assert total > 0 and bad == 0, (bad, total)
