@@ -140,8 +140,7 @@ __device__ __forceinline__ uint32_t swz(uint32_t l, uint32_t swlo, uint32_t swhi
 }
 
 // Barrier for LDS traffic only: wait for this wave's LDS operations, then
-// meet the other waves.  Outstanding global loads (the next chunk's prefetch)
-// and stores stay in flight.
+// meet the other waves.  Outstanding global memory operations stay in flight.
 __device__ __forceinline__ void lds_barrier()
 {
     __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0); vmcnt, expcnt left at their maxima
