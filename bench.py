@@ -68,6 +68,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--n", type=int, default=WORKLOAD["n"])
+    ap.add_argument("--chunk", type=int, default=0, help="chunk qubits C (0 = library default)")
+    ap.add_argument("--reg-qubits", type=int, default=0, help="register qubits per thread r (0 = default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no collectives); use --gpus 1", file=sys.stderr)
@@ -84,7 +86,7 @@ def main():
     log("circuit: %d qubits, %d gates" % (n, len(circ)))
 
     t0 = time.perf_counter()
-    plan = qs.Plan(circ, kmax=kmax)
+    plan = qs.Plan(circ, kmax=kmax, chunk_qubits=args.chunk, reg_qubits=args.reg_qubits)
     plan_s = time.perf_counter() - t0
     st_plan = plan.stats()
     log("plan: %d blocks + %d swap passes, %.3f s" % (st_plan["blocks"], st_plan["swap_passes"], plan_s))

@@ -94,6 +94,48 @@ __device__ __forceinline__ void dense_dispatch(int mask, V (&v)[1 << R], P M)
 }
 #undef QS_DENSE_CASE
 
+// One 2x2 gate on each register bit of MASK, ascending, matrices back to back.
+template <int R, int MASK, int J, typename F, typename V, typename P>
+__device__ __forceinline__ void apply_multi1_from(V (&v)[1 << R], P M)
+{
+    if constexpr (J < R) {
+        if constexpr ((MASK >> J) & 1) {
+            apply_dense<R, (1 << J), F, V, P>(v, M);
+            apply_multi1_from<R, MASK, J + 1, F, V, P>(v, M + 8);
+        } else {
+            apply_multi1_from<R, MASK, J + 1, F, V, P>(v, M);
+        }
+    }
+}
+
+template <int R, int MASK, typename F, typename V, typename P>
+__device__ __forceinline__ void apply_multi1(V (&v)[1 << R], P M)
+{
+    apply_multi1_from<R, MASK, 0, F, V, P>(v, M);
+}
+
+#define QS_MULTI_CASE(MM)                                                                 \
+    case MM:                                                                              \
+        if constexpr ((MM) < (1 << R)) apply_multi1<R, ((MM) < (1 << R) ? (MM) : 1), F, V, P>(v, M); \
+        break;
+
+template <int R, typename F, typename V, typename P>
+__device__ __forceinline__ void multi1_dispatch(int mask, V (&v)[1 << R], P M)
+{
+    switch (mask) {
+        QS_MULTI_CASE(1) QS_MULTI_CASE(2) QS_MULTI_CASE(3) QS_MULTI_CASE(4) QS_MULTI_CASE(5)
+        QS_MULTI_CASE(6) QS_MULTI_CASE(7) QS_MULTI_CASE(8) QS_MULTI_CASE(9) QS_MULTI_CASE(10)
+        QS_MULTI_CASE(11) QS_MULTI_CASE(12) QS_MULTI_CASE(13) QS_MULTI_CASE(14) QS_MULTI_CASE(15)
+        QS_MULTI_CASE(16) QS_MULTI_CASE(17) QS_MULTI_CASE(18) QS_MULTI_CASE(19) QS_MULTI_CASE(20)
+        QS_MULTI_CASE(21) QS_MULTI_CASE(22) QS_MULTI_CASE(23) QS_MULTI_CASE(24) QS_MULTI_CASE(25)
+        QS_MULTI_CASE(26) QS_MULTI_CASE(27) QS_MULTI_CASE(28) QS_MULTI_CASE(29) QS_MULTI_CASE(30)
+        QS_MULTI_CASE(31)
+    default:
+        break;
+    }
+}
+#undef QS_MULTI_CASE
+
 // local index (within the chunk) of thread tid's register 0 in a layout:
 // thread bit j <-> local bit T[j]
 __device__ __forceinline__ uint32_t thread_local_bits(uint32_t tid, const int *__restrict__ T, int tb)
@@ -216,8 +258,11 @@ __device__ __forceinline__ uint64_t chunk_base(uint64_t c, uint64_t cmask, int n
 // One workgroup per chunk: load the chunk into registers (phase 0 layout),
 // run the phases (LDS exchanges between them), store through P_out.  Several
 // workgroups share a CU, so one's HBM traffic overlaps another's arithmetic.
+// Workgroup size limit: 512 threads when each holds at most 8 amplitudes.
+template <int R> struct MaxThreads { static constexpr int value = (R <= 3) ? 512 : 256; };
+
 template <int R, int KMAX, typename F>
-__global__ __launch_bounds__(256) void k_block(typename AmpOf<F>::type *__restrict__ amps,
+__global__ __launch_bounds__(MaxThreads<R>::value) void k_block(typename AmpOf<F>::type *__restrict__ amps,
                                               const int *__restrict__ prog, const F *__restrict__ mats, int n)
 {
     using V = typename AmpOf<F>::type;
@@ -317,7 +362,9 @@ __global__ __launch_bounds__(256) void k_block(typename AmpOf<F>::type *__restri
                 // read through the constant address space: uniform loads of coefficients
                 // become scalar (SMEM) loads instead of per-lane vector loads
                 const CF *M = (const CF *)(uintptr_t)(mats + ((int64_t)mlo | ((int64_t)mhi << 32)));
-                if (kind == OP_DENSE) {
+                if (kind == OP_MULTI1) {
+                    multi1_dispatch<R, F, V, const CF *>(variant, v, M);
+                } else if (kind == OP_DENSE) {
                     dense_dispatch<R, KMAX, F, V, const CF *>(variant, v, M);
                 } else if (kind == OP_SIGN_ROW) {
                     const uint32_t row = pext_u32(tid, (uint32_t)op[1]);
@@ -396,7 +443,7 @@ hipError_t launch_F(qs_state *st, int r, const int *d_prog, const F *d_mats, int
 hipError_t launch_block_prog(qs_state *st, int r, int C, const int *d_prog, const void *d_mats, size_t tab_bytes,
                              int kmax_dense)
 {
-    if (C - r > 8 || C < r || st->n < C) return hipErrorInvalidValue;
+    if (C < r || st->n < C || (1 << (C - r)) > (r <= 3 ? 512 : 256)) return hipErrorInvalidValue;
     if (st->dtype == QS_C64)
         return launch_F<float>(st, r, d_prog, reinterpret_cast<const float *>(d_mats), C, tab_bytes, kmax_dense);
     return launch_F<double>(st, r, d_prog, reinterpret_cast<const double *>(d_mats), C, tab_bytes, kmax_dense);

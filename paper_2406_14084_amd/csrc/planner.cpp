@@ -392,6 +392,64 @@ Op to_kernel_op(const SetOp &s, const Layout &lay, int r)
     return op;
 }
 
+// Local chunk bits an op touches (dense: its register bits; diagonal: its bits).
+uint32_t op_local_mask(const Op &op, const Layout &lay, int r)
+{
+    uint32_t m = 0;
+    if (op.kind == OP_DIAG) {
+        for (int i = 0; i < op.k; ++i) m |= 1u << op.tl[i];
+    } else {
+        for (int j = 0; j < r; ++j)
+            if (op.regmask >> j & 1) m |= 1u << lay.R[j];
+    }
+    return m;
+}
+
+// Group the phase's single-qubit dense ops that act on distinct register bits
+// and are ready together (no earlier op of the phase touches their bits) into
+// one OP_MULTI1; other ops keep their order.  One dispatch then applies up to r
+// gates with compile-time data flow.
+std::vector<Op> group_single_qubit(const std::vector<Op> &ops, const Layout &lay, int r)
+{
+    std::vector<Op> rem = ops, out;
+    while (!rem.empty()) {
+        uint32_t blocked = 0, grp = 0;
+        std::vector<char> take(rem.size(), 0);
+        for (size_t i = 0; i < rem.size(); ++i) {
+            const Op &o = rem[i];
+            const uint32_t lm = op_local_mask(o, lay, r);
+            if (o.kind == OP_DENSE && o.k == 1 && !(lm & blocked) && !(o.regmask & grp)) {
+                take[i] = 1;
+                grp |= (uint32_t)o.regmask;
+            }
+            blocked |= lm;
+        }
+        if (__builtin_popcount(grp) >= 2) {
+            Op g;
+            g.kind = OP_MULTI1;
+            g.regmask = (int)grp;
+            g.k = __builtin_popcount(grp);
+            for (int j = 0; j < r; ++j) {
+                if (!(grp >> j & 1)) continue;
+                for (size_t i = 0; i < rem.size(); ++i)
+                    if (take[i] && rem[i].regmask == (1 << j)) {
+                        g.m.insert(g.m.end(), rem[i].m.begin(), rem[i].m.end());
+                        g.gate_ids.insert(g.gate_ids.end(), rem[i].gate_ids.begin(), rem[i].gate_ids.end());
+                    }
+            }
+            out.push_back(std::move(g));
+            std::vector<Op> rest;
+            for (size_t i = 0; i < rem.size(); ++i)
+                if (!take[i]) rest.push_back(rem[i]);
+            rem.swap(rest);
+        } else {
+            out.push_back(rem.front());
+            rem.erase(rem.begin());
+        }
+    }
+    return out;
+}
+
 Layout make_layout(uint32_t Rmask, int C, int r, const std::vector<int> *store_order)
 {
     Layout lay;
@@ -556,7 +614,8 @@ qs_status build_plan(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan 
     if (C < 1 || C > kMaxChunk) { *err = "qs_fuse: chunk_qubits must be 1..14"; return QS_EINVAL; }
     int L = opts.low_qubits ? opts.low_qubits : 4;
     C = std::min(C, n);
-    r = std::max(r, C - 8);                    // at most 256 threads per workgroup
+    // at most 512 threads per workgroup for r <= 3, 256 otherwise
+    if (C - r > 9 || (r > 3 && C - r > 8)) r = std::max(r, C - 8);
     if (r > kMaxReg) { *err = "qs_fuse: chunk_qubits must be <= 13 (256 threads x 32 registers)"; return QS_EINVAL; }
     r = std::min(r, C);
     if (maxk > r) { *err = "qs_fuse: a gate is wider than the chunk"; return QS_EINVAL; }
@@ -686,7 +745,9 @@ qs_status build_plan(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan 
             prem.swap(rest);
             Phase ph;
             ph.lay = make_layout(R, C, r, nullptr);
-            for (const SetOp &s : PS.fuse_phase(phase_ops, R)) ph.ops.push_back(to_kernel_op(s, ph.lay, r));
+            std::vector<Op> kops;
+            for (const SetOp &s : PS.fuse_phase(phase_ops, R)) kops.push_back(to_kernel_op(s, ph.lay, r));
+            ph.ops = opts.enable_fusion ? group_single_qubit(kops, ph.lay, r) : kops;
             blk.phases.push_back(ph);
             first = false;
         }
@@ -815,6 +876,7 @@ qs_status build_plan(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan 
             for (const Op &op : ph.ops) {
                 ++s.ops;
                 if (op.kind == OP_DIAG) { ++s.ops_diag; s.flops_per_amp += 6.0; }
+                else if (op.kind == OP_MULTI1) { s.ops_dense[1] += op.k; s.flops_per_amp += 16.0 * op.k; }
                 else { ++s.ops_dense[op.k]; s.flops_per_amp += 8.0 * (double)(1 << op.k); }
             }
         }
@@ -907,6 +969,7 @@ void encode_plan(Plan *p)
         for (const Phase &P : blk.phases)
             for (const Op &op : P.ops)
                 if (op.kind == OP_DENSE) bk = std::max(bk, op.k);
+                else if (op.kind == OP_MULTI1) bk = std::max(bk, 1);
         p->block_kmax.push_back(bk);
         std::vector<int32_t> w;
         w.push_back((int32_t)blk.phases.size());
@@ -968,9 +1031,9 @@ void encode_plan(Plan *p)
             }
             for (const Op &op : P.ops) {
                 int64_t moff = (int64_t)p->h_mats.size();
-                if (op.kind == OP_DENSE) {
+                if (op.kind == OP_DENSE || op.kind == OP_MULTI1) {
                     for (const cplx &z : op.m) { p->h_mats.push_back(z.real()); p->h_mats.push_back(z.imag()); }
-                    w.push_back(OP_DENSE | (op.regmask << 8) | (op.k << 16));
+                    w.push_back(op.kind | (op.regmask << 8) | (op.k << 16));
                     w.push_back((int32_t)(uint32_t)(moff & 0xffffffff));
                     w.push_back((int32_t)(uint32_t)(moff >> 32));
                     w.push_back(0);
@@ -1097,7 +1160,7 @@ std::string dump_plan(const Plan &p)
                     for (int j = 0; j < op.k; ++j) os << " " << op.tl[j];
                     os << " " << op.m[0].real() << " " << op.m[0].imag();
                 } else {
-                    os << "U" << op.k;
+                    os << (op.kind == OP_MULTI1 ? "M" : "U") << op.k;
                     for (int j = 0; j < p.r; ++j)
                         if (op.regmask >> j & 1) os << " " << ph.lay.R[j];
                 }

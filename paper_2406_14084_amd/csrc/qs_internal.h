@@ -31,7 +31,8 @@ enum OpKind {
     OP_DIAG_REG = 2,   //   bits all in registers: 2^r entries in register order, uniform
     OP_DIAG_ROW = 3,   //   some bits are thread bits: 2^kt rows of 2^r entries, row = pext(tid, tmask)
     OP_SIGN_REG = 4,   //   entries all +-1, bits in registers: bit m of a mask negates register m
-    OP_SIGN_ROW = 5    //   entries all +-1 with thread bits: one such mask per row
+    OP_SIGN_ROW = 5,   //   entries all +-1 with thread bits: one such mask per row
+    OP_MULTI1 = 6      // one 2x2 gate on each register bit of regmask (they commute), ascending bit order
 };
 
 struct Op {
@@ -116,6 +117,7 @@ void block_features(const Plan &p, std::vector<float> *out);
 //       (slot of (thread, m) = XOR of the thread's bit contributions ^ offset of m)
 //     then per op: 4 words: [kind | (variant << 8) | (k << 16)] [w1] [w2] [w3]
 //       DENSE   : variant = register mask; w1,w2 = matrix offset (scalars, lo/hi)
+//       MULTI1  : variant = register mask; w1,w2 = offset of one 2x2 matrix per set bit, ascending
 //       DIAG_REG: w1,w2 = offset of 2^r entries (register order)
 //       DIAG_ROW: w1 = tmask (thread-index bits of the row); w3 = word offset in the table of
 //                 2^kt rows of 2^r entries (complex128: 4 words each, complex64: 2)

@@ -154,6 +154,20 @@ def replay_block(psi, w, n, R, mats):
                     res = np.einsum("rc,wtc->wtr", M, vin)
                     out[:, :, cols] = res
                 v = out
+            elif kind == 6:       # one 2x2 gate per register bit of the mask, ascending
+                idx = 0
+                for j in range(R):
+                    if not (variant >> j) & 1:
+                        continue
+                    M = mats[moff + 8 * idx:moff + 8 * idx + 8].view(np.complex128).reshape(2, 2)
+                    out = v.copy()
+                    for b0 in range(NR):
+                        if (b0 >> j) & 1:
+                            continue
+                        cols = [b0, b0 | (1 << j)]
+                        out[:, :, cols] = np.einsum("rc,wtc->wtr", M, v[:, :, cols])
+                    v = out
+                    idx += 1
             elif kind == 2:       # register diagonal: uniform entry per register
                 E = mats[moff:moff + 2 * NR].view(np.complex128)
                 v = v * E[None, None, :]
@@ -218,6 +232,7 @@ def replay_plan(plan, n):
     dict(n=12, seed=7, kmax=5, reg_qubits=5), dict(n=11, seed=8, kmax=3, chunk_qubits=7, reg_qubits=3),
     dict(n=3, seed=9, kmax=3), dict(n=1, seed=10, kmax=1), dict(n=12, seed=11, kmax=3, planner=2),
     dict(n=14, seed=12, kmax=4, chunk_qubits=8), dict(n=15, seed=13, kmax=2, chunk_qubits=9, low_qubits=2),
+    dict(n=14, seed=14, kmax=3, chunk_qubits=12, reg_qubits=3),
 ])
 def test_replay_matches_oracle(cfg):
     cfg = dict(cfg)
@@ -277,7 +292,7 @@ def test_replay_uses_every_diagonal_encoding():
             p = qs.Plan(cc, kmax=4)
             kinds |= _op_kinds(p)
             assert np.max(np.abs(replay_plan(p, cc.n) - sim.run(cc))) <= 1e-12
-    assert {0, 2, 3, 4, 5} <= kinds, kinds
+    assert {0, 2, 3, 4, 5, 6} <= kinds, kinds
 
 
 def _op_kinds(p):
