@@ -1,0 +1,149 @@
+"""complex64 path: FP32 state, matrices composed in FP64 and rounded once,
+FP64 readouts.  Parity is stated as a rigorous first-order error bound.
+
+Bound (standard floating-point model, unit roundoff u = 2^-24, gamma_m = m u /
+(1 - m u)): a dense op of k qubits computes each output as a real inner
+product of 2^(k+1) terms, so its error is at most
+    eps_k = (sqrt(2) gamma_(2^(k+1)) + u) * 2^(k/2)
+times the 2-norm of its input (the u term covers the single rounding of the
+matrix to FP32, the 2^(k/2) bounds the 2-norm of |U| for unitary U); a
+diagonal op costs eps_diag = sqrt(2) gamma_2 + u; a +-1 diagonal costs 0.
+Errors of successive (near-)unitary ops add to first order, so
+    ||psi_c64 - psi_exact||_2 <= sum over ops of eps_op   (rigorous bound),
+and max|delta amp| <= ||delta||_2, 1 - fidelity <= ||delta||_2^2.
+The tests assert the measured error is below the rigorous bound and print the
+typical estimate sqrt(sum eps_op^2) beside it.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import sim
+from paper_2406_14084_amd import inputs as I
+from paper_2406_14084_amd import qs
+from tests.gpu_util import need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+def gamma(m):
+    return m * U32 / (1 - m * U32)
+
+
+def eps_dense(k):
+    return (math.sqrt(2) * gamma(2 ** (k + 1)) + U32) * 2 ** (k / 2)
+
+
+EPS_DIAG = math.sqrt(2) * gamma(2) + U32
+
+
+def bound_for(plan):
+    s = plan.stats()
+    terms = []
+    for k in range(1, 6):
+        terms += [eps_dense(k)] * s["ops_dense"][k]
+    terms += [EPS_DIAG] * s["ops_diag"]
+    return sum(terms), math.sqrt(sum(t * t for t in terms))
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return need_gpu()
+
+
+@pytest.mark.parametrize("n,seed,kmax", [(12, 1, 3), (16, 2, 4), (18, 3, 5)])
+def test_c64_random_vs_oracle(torch, n, seed, kmax):
+    c = I.random_dense(n, 120, seed, kmax=3)
+    say("c64 random", n, seed)
+    st = qs.State(n, "c64")
+    st.init_zero()
+    p = qs.Plan(c, kmax=kmax, dtype="c64")
+    st.apply_plan(p)
+    got = st.numpy().astype(np.complex128)
+    want = sim.run(c)
+    d2 = float(np.linalg.norm(got - want))
+    rig, typ = bound_for(p)
+    say("||d||2 = %.3e  max|d| = %.3e  bound %.3e (typical %.3e)" % (d2, np.max(np.abs(got - want)), rig, typ))
+    assert d2 <= rig
+
+
+def test_c64_u3_cx_20q_vs_oracle(torch):
+    """The 32-qubit U3 + CX recipe at 20 qubits, full depth 60."""
+    c = I.random_u3_2q(n=20, depth=60, seed=20003, two="CX")
+    say("c64 u3cx20")
+    st = qs.State(20, "c64")
+    st.init_zero()
+    p = qs.Plan(c, kmax=5, dtype="c64")
+    st.apply_plan(p)
+    got = st.numpy().astype(np.complex128)
+    want = sim.run(c)
+    d2 = float(np.linalg.norm(got - want))
+    rig, typ = bound_for(p)
+    fid = abs(np.vdot(want, got)) ** 2 / np.vdot(got, got).real
+    say("||d||2 = %.3e  max|d| = %.3e  1-F = %.3e  bound %.3e (typical %.3e)"
+        % (d2, np.max(np.abs(got - want)), 1 - fid, rig, typ))
+    assert d2 <= rig and 1 - fid <= rig ** 2 + 1e-12
+
+
+def test_c64_gbg_vs_oracle(torch):
+    c = I.random_dense(14, 40, 9, kmax=5)
+    st = qs.State(14, "c64")
+    st.init_zero()
+    st.apply_circuit_gbg(c)
+    got = st.numpy().astype(np.complex128)
+    want = sim.run(c)
+    rig = sum(eps_dense(g.k) for g in c.gates)
+    assert float(np.linalg.norm(got - want)) <= rig
+
+
+def test_c64_swap_exact(torch):
+    n = 16
+    rng = np.random.default_rng(4)
+    psi = (rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)).astype(np.complex64)
+    st = qs.State(n, "c64")
+    st.tensor.copy_(torch.from_numpy(psi))
+    st.swap_qubits((0, 3, 5), (15, 9, 12))
+    want = psi.astype(np.complex128)
+    sim.swap_qubits(want, (0, 3, 5), (15, 9, 12))
+    assert np.array_equal(st.numpy().astype(np.complex128), want)
+
+
+def test_c64_vs_c128_32q(torch):
+    """Full size: the 32-qubit depth-60 U3 + CX circuit in complex64 (32 GiB)
+    against the same plan run in complex128 on the GPU (64 GiB); the
+    difference must stay inside the complex64 bound (the complex128 run is
+    itself within 1e-12 of exact by the complex128 parity tests)."""
+    n = 32
+    c = I.random_u3_2q(n=n, depth=60, seed=32003, two="CX")
+    say("c64 vs c128 32q")
+    s32 = qs.State(n, "c64")
+    s32.init_zero()
+    p32 = qs.Plan(c, kmax=5, dtype="c64")
+    s32.apply_plan(p32)
+    s64 = qs.State(n, "c128")
+    s64.init_zero()
+    s64.apply_plan(qs.Plan(c, kmax=5))
+    # chunked comparison to bound memory
+    d2 = 0.0
+    dmax = 0.0
+    ov = 0.0 + 0.0j
+    nrm = 0.0
+    step = 1 << 28
+    for i in range(0, 1 << n, step):
+        a = s32.tensor[i:i + step].to(torch.complex128)
+        b = s64.tensor[i:i + step]
+        diff = (a - b).abs()
+        d2 += float((diff ** 2).sum().item())
+        dmax = max(dmax, float(diff.max().item()))
+        ov += complex(torch.vdot(b, a).item())
+        nrm += float((a.abs() ** 2).sum().item())
+    d2 = math.sqrt(d2)
+    fid = abs(ov) ** 2 / nrm
+    rig, typ = bound_for(p32)
+    say("32q: ||d||2 = %.3e max|d| = %.3e 1-F = %.3e bound %.3e typical %.3e" % (d2, dmax, 1 - fid, rig, typ))
+    assert d2 <= rig
