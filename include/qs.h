@@ -230,11 +230,15 @@ typedef struct {
 
 typedef struct qs_batch qs_batch;
 
-/* Pack count instances into device tables and size the launch (tile and
- * chunk choices come from qs_autotune's table when given, else defaults).
- * dtype: QS_C64 (complex64 state, FP64 reductions) or QS_C128.
- * hip_stream: stream for all work.  Allocates device memory for the tables
- * and the per-instance states (workspace), owned by the batch. */
+/* Pack count instances into device tables and a task queue.  An instance of
+ * at most 13 qubits (complex64; 12 for complex128) runs whole in one
+ * workgroup's LDS; a larger one keeps its state in a workspace and is split
+ * into chunk tasks, two passes per layer.  dtype: QS_C64 (complex64 state,
+ * FP64 reductions) or QS_C128.  hip_stream: stream for all work.  Allocates
+ * device memory for the tables, queue and workspace, owned by the batch.
+ * Launch shape defaults to 256 threads and 2 workgroups per CU until
+ * qs_batch_autotune picks one.  Paper: QAOA is one of the benchmark
+ * circuits of Sec. VI-A (Table II); batching is this library's addition. */
 QS_API qs_status qs_batch_qaoa_create(int count, const qs_qaoa_instance *inst, qs_dtype dtype,
                                void *hip_stream, qs_batch **out);
 
@@ -248,6 +252,11 @@ QS_API qs_status qs_batch_qaoa_run(qs_batch *b, double *out_dev, int use_graph);
 QS_API qs_status qs_batch_qaoa_run_sequential(qs_batch *b, double *out_dev);
 
 QS_API qs_status qs_batch_free(qs_batch *b);
+
+/* Nonzero *err if a pass of a large instance gave up waiting for its
+ * previous pass (a bounded spin in the persistent kernel; its results are
+ * then invalid).  Synchronises the stream. */
+QS_API qs_status qs_batch_error(qs_batch *b, int *err);
 
 /* Choose tile/chunk parameters for the batched kernel by timing candidates
  * on the device for the given batch; writes the chosen config index and

@@ -3,11 +3,6 @@
 #include "qs_internal.h"
 
 extern "C" {
-qs_status qs_batch_qaoa_create(int, const qs_qaoa_instance *, qs_dtype, void *, qs_batch **) { qs::set_error("batched QAOA: not built"); return QS_EUNSUPPORTED; }
-qs_status qs_batch_qaoa_run(qs_batch *, double *, int) { qs::set_error("batched QAOA: not built"); return QS_EUNSUPPORTED; }
-qs_status qs_batch_qaoa_run_sequential(qs_batch *, double *) { qs::set_error("batched QAOA: not built"); return QS_EUNSUPPORTED; }
-qs_status qs_batch_free(qs_batch *) { return QS_OK; }
-qs_status qs_batch_autotune(qs_batch *, int *, double *) { qs::set_error("batched QAOA: not built"); return QS_EUNSUPPORTED; }
 qs_status qs_costmodel_create(uint64_t, void *, qs_costmodel **) { qs::set_error("cost model: not built"); return QS_EUNSUPPORTED; }
 qs_status qs_costmodel_free(qs_costmodel *) { return QS_OK; }
 qs_status qs_costmodel_get_params(const qs_costmodel *, float *) { return QS_EUNSUPPORTED; }

@@ -1,0 +1,561 @@
+// k_qaoa.hip -- many small QAOA MaxCut circuits of uneven size in one
+// persistent launch.
+//
+// Circuit per instance (QAOA, named among the paper's benchmark circuits,
+// Sec. VI-A Table II): |+>^n, then for each of p layers the cost layer
+// a_z <- exp(-i gamma C(z)) a_z with C(z) = number of cut edges, and RX(2 beta)
+// on every qubit; output <C> = sum_z |a_z|^2 C(z) accumulated in FP64.
+//
+// gfx950 design:
+//   - one persistent kernel pops tasks from an atomic queue; every workgroup
+//     leaves when the queue is empty;
+//   - an instance of at most CB qubits is one task: its whole state lives in
+//     LDS (2^CB amplitudes), C(z) is tabulated once in LDS and reused by every
+//     layer and by the final reduction;
+//   - a larger instance keeps its state in a workspace in HBM and is split
+//     into chunk tasks of 2^CB amplitudes per pass (two passes per layer: the
+//     low CB qubits, then the remaining high ones with a few low ones); a pass
+//     waits (bounded spin) for the instance's previous pass through a per-
+//     instance completion counter, with agent-scope release/acquire fences;
+//   - tasks are queued so that a task only ever waits for tasks queued before
+//     it, which running workgroups have already taken: no deadlock.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "amp.h"
+#include "qs_internal.h"
+
+namespace qs {
+namespace {
+
+struct QInst {
+    int n, nedges, p, large;
+    int edge_off;      // into the edge array (pairs)
+    int tab_off;       // into the per-instance table (scalars): per layer (nedges+1) phases (cos, -sin) then (cos b, sin b)
+    long long work_off;  // amplitude offset of the state in the workspace (large only)
+    int res;           // output index
+    int pad;
+};
+
+struct QTask {
+    int inst, pass, chunk, pad;
+};
+
+constexpr unsigned kSpinLimit = 1u << 24;   // ~1 s of polling before giving up (error flag)
+
+template <typename F, typename V>
+__device__ __forceinline__ void rx_pair(V &a0, V &a1, F c, F s)
+{
+    // RX(2b) = [[c, -i s], [-i s, c]], c = cos b, s = sin b
+    const V x = a0, y = a1;
+    a0.x = qfma(c, x.x, s * y.y);
+    a0.y = qfma(c, x.y, -s * y.x);
+    a1.x = qfma(c, y.x, s * x.y);
+    a1.y = qfma(c, y.y, -s * x.x);
+}
+
+__device__ __forceinline__ int cut_value(uint64_t z, const int2 *e, int ne)
+{
+    int c = 0;
+    for (int i = 0; i < ne; ++i) c += (int)(((z >> e[i].x) ^ (z >> e[i].y)) & 1ull);
+    return c;
+}
+
+// Global amplitude index of local index l in chunk j of a pass.
+__device__ __forceinline__ uint64_t pass_index(uint32_t l, uint64_t j, int n, int CB, bool second)
+{
+    if (!second) return (j << CB) | l;
+    const int m = n - CB;               // high qubits CB..n-1 live in local bits CB-m..CB-1
+    const uint32_t lowmask = (1u << (CB - m)) - 1u;
+    return (uint64_t)(l & lowmask) | (j << (CB - m)) | ((uint64_t)(l >> (CB - m)) << CB);
+}
+
+template <int THREADS, int CB, typename F>
+__global__ __launch_bounds__(THREADS) void k_qaoa(const QInst *__restrict__ inst, const QTask *__restrict__ tasks,
+                                                  int task_begin, int ntasks, const int2 *__restrict__ edges,
+                                                  const F *__restrict__ tab, typename AmpOf<F>::type *__restrict__ work,
+                                                  unsigned *__restrict__ next, unsigned *__restrict__ done,
+                                                  unsigned *__restrict__ err, double *__restrict__ res)
+{
+    using V = typename AmpOf<F>::type;
+    constexpr int NA = 1 << CB;
+    __shared__ V st[NA];
+    __shared__ unsigned char cz[NA];
+    __shared__ int2 se[64];
+    __shared__ double red[THREADS / 64];
+    __shared__ int s_task;
+    const int tid = threadIdx.x;
+
+    for (;;) {
+        if (tid == 0) s_task = (int)atomicAdd(next, 1u);
+        __syncthreads();
+        const int t = s_task;
+        __syncthreads();
+        if (t >= ntasks) break;
+        const QTask tk = tasks[task_begin + t];
+        const QInst I = inst[tk.inst];
+        for (int i = tid; i < I.nedges; i += THREADS) se[i] = edges[I.edge_off + i];
+        const F *T = tab + I.tab_off;
+        const int layer_scalars = 2 * (I.nedges + 1) + 2;
+
+        if (!I.large) {
+            // ---- whole instance in LDS
+            const int na = 1 << I.n;
+            __syncthreads();
+            const F amp0 = (F)(1.0 / sqrt((double)na));
+            for (int l = tid; l < na; l += THREADS) {
+                st[l].x = amp0;
+                st[l].y = (F)0;
+                cz[l] = (unsigned char)cut_value((uint64_t)l, se, I.nedges);
+            }
+            __syncthreads();
+            for (int layer = 0; layer < I.p; ++layer) {
+                const F *L = T + layer * layer_scalars;
+                for (int l = tid; l < na; l += THREADS) {
+                    const int c = cz[l];
+                    st[l] = cmul<F, V>(L[2 * c], L[2 * c + 1], st[l]);
+                }
+                const F cb = L[2 * (I.nedges + 1)], sb = L[2 * (I.nedges + 1) + 1];
+                for (int q = 0; q < I.n; ++q) {
+                    __syncthreads();
+                    for (int pi = tid; pi < na / 2; pi += THREADS) {
+                        const int l0 = ((pi >> q) << (q + 1)) | (pi & ((1 << q) - 1));
+                        rx_pair<F, V>(st[l0], st[l0 | (1 << q)], cb, sb);
+                    }
+                }
+                __syncthreads();
+            }
+            double acc = 0.0;
+            for (int l = tid; l < na; l += THREADS) {
+                const double x = (double)st[l].x, y = (double)st[l].y;
+                acc += (x * x + y * y) * (double)cz[l];
+            }
+            for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+            if ((tid & 63) == 0) red[tid >> 6] = acc;
+            __syncthreads();
+            if (tid == 0) {
+                double s = 0.0;
+                for (int w = 0; w < THREADS / 64; ++w) s += red[w];
+                res[I.res] = s;
+            }
+            __syncthreads();
+            continue;
+        }
+
+        // ---- one chunk of a large instance, one pass
+        const int nch = 1 << (I.n - CB);
+        const bool second = (tk.pass & 1) != 0;
+        const int layer = tk.pass >> 1;
+        const bool first_pass = (tk.pass == 0);
+        const bool last_pass = (tk.pass == 2 * I.p - 1);
+        if (tk.pass > 0 && tid == 0) {
+            const unsigned need = (unsigned)tk.pass * (unsigned)nch;
+            unsigned spins = 0;
+            while (__hip_atomic_load(&done[tk.inst], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > kSpinLimit) {
+                    atomicOr(err, 1u);
+                    break;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        __syncthreads();
+        V *g = work + I.work_off;
+        const F amp0 = (F)(1.0 / sqrt(ldexp(1.0, I.n)));
+        for (int l = tid; l < NA; l += THREADS) {
+            const uint64_t z = pass_index((uint32_t)l, (uint64_t)tk.chunk, I.n, CB, second);
+            if (first_pass) {
+                st[l].x = amp0;
+                st[l].y = (F)0;
+            } else {
+                st[l] = g[z];
+            }
+            if (!second || last_pass) cz[l] = (unsigned char)cut_value(z, se, I.nedges);
+        }
+        __syncthreads();
+        const F *L = T + layer * layer_scalars;
+        const F cb = L[2 * (I.nedges + 1)], sb = L[2 * (I.nedges + 1) + 1];
+        int qlo, qhi;
+        if (!second) {
+            for (int l = tid; l < NA; l += THREADS) {
+                const int c = cz[l];
+                st[l] = cmul<F, V>(L[2 * c], L[2 * c + 1], st[l]);
+            }
+            qlo = 0;
+            qhi = CB;
+        } else {
+            qlo = CB - (I.n - CB);
+            qhi = CB;
+        }
+        for (int q = qlo; q < qhi; ++q) {
+            __syncthreads();
+            for (int pi = tid; pi < NA / 2; pi += THREADS) {
+                const int l0 = ((pi >> q) << (q + 1)) | (pi & ((1 << q) - 1));
+                rx_pair<F, V>(st[l0], st[l0 | (1 << q)], cb, sb);
+            }
+        }
+        __syncthreads();
+        if (last_pass) {
+            double acc = 0.0;
+            for (int l = tid; l < NA; l += THREADS) {
+                const double x = (double)st[l].x, y = (double)st[l].y;
+                acc += (x * x + y * y) * (double)cz[l];
+            }
+            for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+            if ((tid & 63) == 0) red[tid >> 6] = acc;
+            __syncthreads();
+            if (tid == 0) {
+                double s = 0.0;
+                for (int w = 0; w < THREADS / 64; ++w) s += red[w];
+                atomicAdd(&res[I.res], s);
+            }
+        } else {
+            for (int l = tid; l < NA; l += THREADS) {
+                const uint64_t z = pass_index((uint32_t)l, (uint64_t)tk.chunk, I.n, CB, second);
+                g[z] = st[l];
+            }
+            // make the chunk visible to whichever workgroup runs the next pass
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        }
+        __syncthreads();
+        if (tid == 0) atomicAdd(&done[tk.inst], 1u);
+        __syncthreads();
+    }
+}
+
+// Zero the queue counter(s), the completion counters, the error flag and the
+// results (a kernel rather than a memset, so the launch can sit in a graph).
+__global__ void k_qaoa_reset(unsigned *ctr, int nctr, double *res, int nres)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nctr) ctr[i] = 0u;
+    if (i < nres) res[i] = 0.0;
+}
+
+}  // namespace
+}  // namespace qs
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct qs_batch {
+    int count = 0;
+    qs_dtype dtype = QS_C64;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    void *d_inst = nullptr, *d_tasks = nullptr, *d_seq_tasks = nullptr, *d_edges = nullptr, *d_tab = nullptr;
+    void *d_work = nullptr, *d_ctr = nullptr;
+    int ntasks = 0;
+    std::vector<int> seq_begin, seq_count;   // per instance: its tasks in d_seq_tasks
+    int nctr = 0;                            // [0] next, [1] err, [2..2+count) done, then one "next" per sequential launch
+    int threads = 256;                       // autotuned
+    int grid_per_cu = 2;                     // autotuned
+    int cus = 256;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    double *graph_out = nullptr;
+    // graphs are captured and replayed on a stream of the batch's own (the
+    // caller's stream may be the legacy default stream, which cannot be
+    // captured), ordered against the caller's stream with events
+    hipStream_t gstream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+};
+
+namespace {
+
+constexpr int kCB64 = 13, kCB128 = 12;
+
+template <typename F>
+hipError_t launch_qaoa(qs_batch *b, const void *tasks, int begin, int ntasks, unsigned *next, double *out, int threads,
+                       int grid)
+{
+    using namespace qs;
+    using V = typename AmpOf<F>::type;
+    constexpr int CB = sizeof(F) == 4 ? kCB64 : kCB128;
+    unsigned *ctr = reinterpret_cast<unsigned *>(b->d_ctr);
+    const QInst *I = reinterpret_cast<const QInst *>(b->d_inst);
+    const QTask *T = reinterpret_cast<const QTask *>(tasks);
+    const int2 *E = reinterpret_cast<const int2 *>(b->d_edges);
+    const F *tab = reinterpret_cast<const F *>(b->d_tab);
+    V *work = reinterpret_cast<V *>(b->d_work);
+    if (threads == 512)
+        hipLaunchKernelGGL((k_qaoa<512, CB, F>), dim3(grid), dim3(512), 0, b->stream, I, T, begin, ntasks, E, tab, work,
+                           next, ctr + 2, ctr + 1, out);
+    else
+        hipLaunchKernelGGL((k_qaoa<256, CB, F>), dim3(grid), dim3(256), 0, b->stream, I, T, begin, ntasks, E, tab, work,
+                           next, ctr + 2, ctr + 1, out);
+    return hipGetLastError();
+}
+
+hipError_t run_batch(qs_batch *b, double *out, int threads, int grid_per_cu)
+{
+    using namespace qs;
+    unsigned *ctr = reinterpret_cast<unsigned *>(b->d_ctr);
+    const int nz = std::max(2 + b->count, b->count);
+    hipLaunchKernelGGL(k_qaoa_reset, dim3((nz + 255) / 256), dim3(256), 0, b->stream, ctr, 2 + b->count, out, b->count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int grid = std::max(1, std::min(b->ntasks, b->cus * grid_per_cu));
+    if (b->dtype == QS_C64) return launch_qaoa<float>(b, b->d_tasks, 0, b->ntasks, ctr, out, threads, grid);
+    return launch_qaoa<double>(b, b->d_tasks, 0, b->ntasks, ctr, out, threads, grid);
+}
+
+}  // namespace
+
+extern "C" {
+
+qs_status qs_batch_qaoa_create(int count, const qs_qaoa_instance *inst, qs_dtype dtype, void *hip_stream,
+                               qs_batch **out)
+{
+    using namespace qs;
+    if (!out || count < 1 || !inst) { set_error("qs_batch_qaoa_create: bad arguments"); return QS_EINVAL; }
+    if (dtype != QS_C64 && dtype != QS_C128) { set_error("qs_batch_qaoa_create: bad dtype"); return QS_EINVAL; }
+    const int CB = dtype == QS_C64 ? kCB64 : kCB128;
+    const size_t abytes = dtype == QS_C64 ? 8 : 16;
+    for (int i = 0; i < count; ++i) {
+        const qs_qaoa_instance &q = inst[i];
+        if (q.n < 2 || q.n > 20 || q.nedges < 0 || q.nedges > 64 || q.p < 1 || q.p > 64 || (q.nedges && !q.edges) ||
+            !q.gammas || !q.betas) {
+            set_error("qs_batch_qaoa_create: instance " + std::to_string(i) + " out of range (n 2..20, edges <= 64, p 1..64)");
+            return QS_EINVAL;
+        }
+        for (int e = 0; e < 2 * q.nedges; ++e)
+            if (q.edges[e] < 0 || q.edges[e] >= q.n) { set_error("qs_batch_qaoa_create: bad edge"); return QS_EINVAL; }
+        if (q.n > CB && q.n - CB > CB) { set_error("qs_batch_qaoa_create: instance too large"); return QS_EINVAL; }
+    }
+    qs_batch *b = new qs_batch();
+    b->count = count;
+    b->dtype = dtype;
+    b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    (void)hipGetDevice(&b->device);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, b->device) == hipSuccess && prop.multiProcessorCount > 0) b->cus = prop.multiProcessorCount;
+
+    // descriptors, edges, tables (phase table per layer computed in FP64, rounded once)
+    std::vector<QInst> I(count);
+    std::vector<int> E;
+    std::vector<double> tab;
+    long long work = 0;
+    for (int i = 0; i < count; ++i) {
+        const qs_qaoa_instance &q = inst[i];
+        QInst &d = I[i];
+        d.n = q.n;
+        d.nedges = q.nedges;
+        d.p = q.p;
+        d.large = q.n > CB ? 1 : 0;
+        d.edge_off = (int)(E.size() / 2);
+        for (int e = 0; e < 2 * q.nedges; ++e) E.push_back(q.edges[e]);
+        d.tab_off = (int)tab.size();
+        for (int l = 0; l < q.p; ++l) {
+            for (int c = 0; c <= q.nedges; ++c) {
+                tab.push_back(std::cos(q.gammas[l] * c));
+                tab.push_back(-std::sin(q.gammas[l] * c));
+            }
+            tab.push_back(std::cos(q.betas[l]));
+            tab.push_back(std::sin(q.betas[l]));
+        }
+        d.work_off = d.large ? work : 0;
+        if (d.large) work += 1ll << q.n;
+        d.res = i;
+        d.pad = 0;
+    }
+    // queue: passes of the large instances interleaved, independent small
+    // instances (largest first) spread between the passes
+    std::vector<int> large, small;
+    for (int i = 0; i < count; ++i) (I[i].large ? large : small).push_back(i);
+    auto by_n = [&](int a, int c) { return I[a].n > I[c].n || (I[a].n == I[c].n && a < c); };
+    std::sort(large.begin(), large.end(), by_n);
+    std::sort(small.begin(), small.end(), by_n);
+    int maxpass = 0;
+    for (int i : large) maxpass = std::max(maxpass, 2 * I[i].p);
+    std::vector<QTask> tasks;
+    size_t si = 0;
+    for (int s = 0; s < maxpass; ++s) {
+        for (int i : large) {
+            if (s >= 2 * I[i].p) continue;
+            for (int j = 0; j < (1 << (I[i].n - CB)); ++j) tasks.push_back({i, s, j, 0});
+        }
+        const size_t take = (small.size() * (size_t)(s + 1)) / (size_t)maxpass;
+        for (; si < take; ++si) tasks.push_back({small[si], 0, 0, 0});
+    }
+    for (; si < small.size(); ++si) tasks.push_back({small[si], 0, 0, 0});
+    b->ntasks = (int)tasks.size();
+    // per-instance task lists for the sequential reference
+    std::vector<QTask> seq;
+    b->seq_begin.resize(count);
+    b->seq_count.resize(count);
+    for (int i = 0; i < count; ++i) {
+        b->seq_begin[i] = (int)seq.size();
+        if (I[i].large) {
+            for (int s = 0; s < 2 * I[i].p; ++s)
+                for (int j = 0; j < (1 << (I[i].n - CB)); ++j) seq.push_back({i, s, j, 0});
+        } else {
+            seq.push_back({i, 0, 0, 0});
+        }
+        b->seq_count[i] = (int)seq.size() - b->seq_begin[i];
+    }
+    b->nctr = 2 + count + count;
+    qs_status rc = QS_OK;
+    auto alloc = [&](void **p, size_t bytes, const void *src, const char *what) {
+        if (rc) return;
+        hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 16));
+        if (e == hipSuccess && src && bytes) e = hipMemcpy(*p, src, bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) rc = hip_fail(e, what);
+    };
+    alloc(&b->d_inst, I.size() * sizeof(QInst), I.data(), "qs_batch_qaoa_create: descriptors");
+    alloc(&b->d_tasks, tasks.size() * sizeof(QTask), tasks.data(), "qs_batch_qaoa_create: tasks");
+    alloc(&b->d_seq_tasks, seq.size() * sizeof(QTask), seq.data(), "qs_batch_qaoa_create: tasks");
+    alloc(&b->d_edges, E.size() * sizeof(int), E.data(), "qs_batch_qaoa_create: edges");
+    if (dtype == QS_C64) {
+        std::vector<float> t32(tab.begin(), tab.end());
+        alloc(&b->d_tab, t32.size() * sizeof(float), t32.data(), "qs_batch_qaoa_create: tables");
+    } else {
+        alloc(&b->d_tab, tab.size() * sizeof(double), tab.data(), "qs_batch_qaoa_create: tables");
+    }
+    alloc(&b->d_work, (size_t)work * abytes, nullptr, "qs_batch_qaoa_create: workspace");
+    alloc(&b->d_ctr, (size_t)b->nctr * sizeof(unsigned), nullptr, "qs_batch_qaoa_create: counters");
+    if (rc) {
+        qs_batch_free(b);
+        return rc;
+    }
+    *out = b;
+    return QS_OK;
+}
+
+qs_status qs_batch_qaoa_run(qs_batch *b, double *out_dev, int use_graph)
+{
+    using namespace qs;
+    if (!b || !out_dev) { set_error("qs_batch_qaoa_run: null argument"); return QS_EINVAL; }
+    (void)hipSetDevice(b->device);
+    if (!use_graph) {
+        hipError_t e = run_batch(b, out_dev, b->threads, b->grid_per_cu);
+        if (e != hipSuccess) return hip_fail(e, "qs_batch_qaoa_run");
+        return QS_OK;
+    }
+    if (!b->gstream) {
+        hipError_t e = hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "qs_batch_qaoa_run: graph stream");
+    }
+    if (!b->gexec || b->graph_out != out_dev) {
+        if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+        if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+        hipStream_t user = b->stream;
+        b->stream = b->gstream;
+        hipError_t e = hipStreamBeginCapture(b->gstream, hipStreamCaptureModeThreadLocal);
+        hipError_t e2 = (e == hipSuccess) ? run_batch(b, out_dev, b->threads, b->grid_per_cu) : hipSuccess;
+        hipError_t e3 = (e == hipSuccess) ? hipStreamEndCapture(b->gstream, &b->graph) : hipSuccess;
+        b->stream = user;
+        if (e != hipSuccess) return hip_fail(e, "qs_batch_qaoa_run: begin capture");
+        if (e2 != hipSuccess) return hip_fail(e2, "qs_batch_qaoa_run: capture");
+        if (e3 != hipSuccess) return hip_fail(e3, "qs_batch_qaoa_run: end capture");
+        e = hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) return hip_fail(e, "qs_batch_qaoa_run: instantiate");
+        b->graph_out = out_dev;
+    }
+    hipError_t e = hipEventRecord(b->ev_in, b->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->gstream, b->ev_in, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(b->gexec, b->gstream);
+    if (e == hipSuccess) e = hipEventRecord(b->ev_out, b->gstream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_out, 0);
+    if (e != hipSuccess) return hip_fail(e, "qs_batch_qaoa_run: graph launch");
+    return QS_OK;
+}
+
+qs_status qs_batch_qaoa_run_sequential(qs_batch *b, double *out_dev)
+{
+    using namespace qs;
+    if (!b || !out_dev) { set_error("qs_batch_qaoa_run_sequential: null argument"); return QS_EINVAL; }
+    (void)hipSetDevice(b->device);
+    unsigned *ctr = reinterpret_cast<unsigned *>(b->d_ctr);
+    hipLaunchKernelGGL(k_qaoa_reset, dim3((b->nctr + 255) / 256), dim3(256), 0, b->stream, ctr, b->nctr, out_dev, b->count);
+    hipError_t e = hipGetLastError();
+    for (int i = 0; i < b->count && e == hipSuccess; ++i) {
+        unsigned *next = ctr + 2 + b->count + i;     // one queue counter per launch
+        const int grid = std::max(1, std::min(b->seq_count[i], b->cus * b->grid_per_cu));
+        if (b->dtype == QS_C64)
+            e = launch_qaoa<float>(b, b->d_seq_tasks, b->seq_begin[i], b->seq_count[i], next, out_dev, b->threads, grid);
+        else
+            e = launch_qaoa<double>(b, b->d_seq_tasks, b->seq_begin[i], b->seq_count[i], next, out_dev, b->threads, grid);
+    }
+    if (e != hipSuccess) return hip_fail(e, "qs_batch_qaoa_run_sequential");
+    return QS_OK;
+}
+
+qs_status qs_batch_autotune(qs_batch *b, int *chosen, double *best_ms)
+{
+    using namespace qs;
+    if (!b) { set_error("qs_batch_autotune: null batch"); return QS_EINVAL; }
+    (void)hipSetDevice(b->device);
+    double *tmp = nullptr;
+    hipError_t e = hipMalloc(&tmp, sizeof(double) * b->count);
+    if (e != hipSuccess) return hip_fail(e, "qs_batch_autotune: hipMalloc");
+    const int cand[][2] = {{256, 1}, {256, 2}, {256, 4}, {512, 1}, {512, 2}};
+    const int ncand = (int)(sizeof(cand) / sizeof(cand[0]));
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    double best = 1e30;
+    int bi = 0;
+    for (int c = 0; c < ncand && e == hipSuccess; ++c) {
+        float tbest = 1e30f;
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+            e = hipEventRecord(e0, b->stream);
+            if (e == hipSuccess) e = run_batch(b, tmp, cand[c][0], cand[c][1]);
+            if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (rep > 0) tbest = std::min(tbest, ms);     // first run warms up
+        }
+        if (e == hipSuccess && tbest < best) { best = tbest; bi = c; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return hip_fail(e, "qs_batch_autotune");
+    b->threads = cand[bi][0];
+    b->grid_per_cu = cand[bi][1];
+    if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+    if (chosen) *chosen = bi;
+    if (best_ms) *best_ms = best;
+    return QS_OK;
+}
+
+qs_status qs_batch_free(qs_batch *b)
+{
+    if (!b) return QS_OK;
+    (void)hipSetDevice(b->device);
+    (void)hipStreamSynchronize(b->stream);
+    if (b->gstream) (void)hipStreamSynchronize(b->gstream);
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->gstream) (void)hipStreamDestroy(b->gstream);
+    for (void *p : {b->d_inst, b->d_tasks, b->d_seq_tasks, b->d_edges, b->d_tab, b->d_work, b->d_ctr})
+        if (p) (void)hipFree(p);
+    delete b;
+    return QS_OK;
+}
+
+qs_status qs_batch_error(qs_batch *b, int *err)
+{
+    using namespace qs;
+    if (!b || !err) { set_error("qs_batch_error: null argument"); return QS_EINVAL; }
+    unsigned v = 0;
+    hipError_t e = hipMemcpyAsync(&v, reinterpret_cast<unsigned *>(b->d_ctr) + 1, sizeof(unsigned), hipMemcpyDeviceToHost,
+                                  b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(e, "qs_batch_error");
+    *err = (int)v;
+    return QS_OK;
+}
+
+}  // extern "C"

@@ -83,6 +83,7 @@ SIGNATURES = {
     "qs_batch_qaoa_run_sequential": (C.c_int, [_P, _P]),
     "qs_batch_free": (C.c_int, [_P]),
     "qs_batch_autotune": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+    "qs_batch_error": (C.c_int, [_P, C.POINTER(C.c_int)]),
     "qs_costmodel_create": (C.c_int, [C.c_uint64, _P, C.POINTER(_P)]),
     "qs_costmodel_free": (C.c_int, [_P]),
     "qs_costmodel_get_params": (C.c_int, [_P, C.POINTER(C.c_float)]),
@@ -310,3 +311,56 @@ class Plan:
             check(lib().qs_plan_layout(self.h, s, perm, None))
             out.append(list(perm))
         return out
+
+
+class QaoaBatch:
+    """Many MaxCut QAOA instances (inputs.QaoaInstance) run by one persistent
+    launch; results are <C> per instance in FP64."""
+
+    def __init__(self, instances, dtype="c64", stream=None):
+        torch = _torch()
+        self.count = len(instances)
+        self._keep = []
+        arr = (QaoaInst_C * self.count)()
+        for i, q in enumerate(instances):
+            e = np.ascontiguousarray(np.array(q.edges, dtype=np.int32).reshape(-1))
+            g = np.ascontiguousarray(q.gammas, dtype=np.float64)
+            b = np.ascontiguousarray(q.betas, dtype=np.float64)
+            self._keep += [e, g, b]
+            arr[i] = QaoaInst_C(q.n, len(q.edges), len(g), _ip(e), _dp(g), _dp(b))
+        self.dtype = QS_C64 if dtype in ("c64", "complex64", QS_C64) else QS_C128
+        h = C.c_void_p()
+        check(lib().qs_batch_qaoa_create(self.count, arr, self.dtype, _stream_ptr(stream), C.byref(h)))
+        self.h = h
+        self.out = torch.zeros(self.count, dtype=torch.float64, device="cuda")
+
+    def run(self, graph=False):
+        check(lib().qs_batch_qaoa_run(self.h, C.c_void_p(self.out.data_ptr()), int(graph)))
+        return self.out
+
+    def run_sequential(self, out=None):
+        out = self.out if out is None else out
+        check(lib().qs_batch_qaoa_run_sequential(self.h, C.c_void_p(out.data_ptr())))
+        return out
+
+    def autotune(self):
+        ch = C.c_int()
+        ms = C.c_double()
+        check(lib().qs_batch_autotune(self.h, C.byref(ch), C.byref(ms)))
+        return ch.value, ms.value
+
+    def error(self):
+        e = C.c_int()
+        check(lib().qs_batch_error(self.h, C.byref(e)))
+        return e.value
+
+    def close(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            lib().qs_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
