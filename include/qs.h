@@ -82,6 +82,7 @@ typedef struct {
     const qs_costmodel *cost_model;  /* required when planner == 1, else NULL */
     qs_dtype dtype;       /* precision the plan will run at (matrices are rounded once, after FP64 composition) */
     int reg_qubits;       /* r: register-resident qubits per thread (4 or 5); 0 = default */
+    int no_mfma;          /* complex64: 1 keeps dense ops of 4-5 qubits on vector FMA instead of matrix cores */
 } qs_plan_opts;
 
 /* One Pauli string times a real coefficient.  Per qubit q the letter is
@@ -110,6 +111,11 @@ typedef struct {
     double flops_per_amp; /* sum over ops of algorithmic flops per amplitude (dense k: 8*2^k, diagonal: 6) */
     double hbm_bytes;     /* (blocks + swap_passes) * 2 * 2^n * bytes per amplitude */
     double plan_seconds;  /* host time spent in qs_fuse */
+    int planner;          /* planner that produced the plan: 0 heuristic, 1 learned, 2 gate by gate */
+    int candidates;       /* plans compared (1 unless the learned planner ran) */
+    double predicted_ms;  /* learned planner: predicted time of the chosen plan, else -1 */
+    double predicted_heuristic_ms; /* learned planner: predicted time of the heuristic plan, else -1 */
+    int ops_mfma;         /* dense ops (counted in ops_dense too) that run on matrix cores */
 } qs_plan_stats;
 
 /* ---- state handles ------------------------------------------------------ */

@@ -20,6 +20,7 @@
 //   - the write-back may permute the chunk's bits (P_out), which performs a
 //     qubit swap at no extra HBM pass.
 #include <algorithm>
+#include <type_traits>
 
 #include "amp.h"
 #include "qs_internal.h"
@@ -135,6 +136,98 @@ __device__ __forceinline__ void multi1_dispatch(int mask, V (&v)[1 << R], P M)
     }
 }
 #undef QS_MULTI_CASE
+
+// bits of v selected by MASK, packed to the low end (compile time)
+template <int MASK>
+__device__ __forceinline__ constexpr int pext_c(int v)
+{
+    int r = 0, i = 0;
+    for (int b = 0; b < 8; ++b)
+        if ((MASK >> b) & 1) { r |= ((v >> b) & 1) << i; ++i; }
+    return r;
+}
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// Complex64 dense op of K = 4 or 5 of the five register bits on the matrix
+// cores.  The wave's 64 * 2^(5-K) vectors of 2^K amplitudes form the columns
+// of B; the op is the real product
+//     [Re w; Im w] = [[Re U, -Im U], [Im U, Re U]] [Re v; Im v]
+// computed by v_mfma_f32_32x32x2f32 (FP32 products, FP32 accumulation) on
+// tiles of 32 vectors, with rows and columns interleaved (row 2i + 0/1 = real
+// / imaginary part of element i).  The amplitudes travel registers -> the
+// wave's own LDS region (S[element][vector]) -> B operands, and the results
+// D -> S -> registers.  Operand layouts of the 32x32x2 product: A[i][k] and
+// B[k][j] sit in lane i + 32 k (resp. j + 32 k); D[i][j] in lane j + 32 ((i / 4) % 2),
+// accumulator 4 (i / 8) + i % 4.  A comes from the plan, already in lane
+// order: A[(mb * 2^K + s) * 64 + lane] for row block mb and step s, where
+// step s feeds part s % 2 of element 2 (s / 2) + lane / 32.
+template <int MASK>
+__device__ __forceinline__ void apply_mfma(c64 (&v)[32], const float *__restrict__ A, c64 *__restrict__ S, uint32_t lane)
+{
+    constexpr int K = __builtin_popcount(MASK);
+    constexpr int D = 1 << K;            // elements per vector
+    constexpr int NV = 64 << (5 - K);    // vectors of the wave
+    constexpr int NMB = D / 16;          // blocks of 32 real rows
+    constexpr int NT = NV / 32;          // tiles of 32 vectors
+    constexpr int REST = 31 & ~MASK;
+#pragma unroll
+    for (int m = 0; m < 32; ++m) S[pext_c<MASK>(m) * NV + pext_c<REST>(m) * 64 + lane] = v[m];
+    asm volatile("" ::: "memory");       // LDS ops of a wave run in order; keep the compiler from reordering
+    float a[NMB][D];
+#pragma unroll
+    for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+        for (int s = 0; s < D; ++s) a[mb][s] = A[(mb * D + s) * 64 + lane];
+    const uint32_t n = lane & 31u, h = lane >> 5;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        c64 b[D / 2];
+#pragma unroll
+        for (int u = 0; u < D / 2; ++u) b[u] = S[(2 * u + h) * NV + 32 * t + n];
+        floatx16 acc[NMB];
+#pragma unroll
+        for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+            for (int g = 0; g < 16; ++g) acc[mb][g] = 0.f;
+#pragma unroll
+        for (int u = 0; u < D / 2; ++u)
+#pragma unroll
+            for (int mb = 0; mb < NMB; ++mb) {
+                acc[mb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[mb][2 * u], b[u].x, acc[mb], 0, 0, 0);
+                acc[mb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[mb][2 * u + 1], b[u].y, acc[mb], 0, 0, 0);
+            }
+        // accumulators g, g + 1 (g even) are rows 8 (g / 4) + 4 h + g % 4 and the
+        // next one: the real and imaginary parts of one output element
+#pragma unroll
+        for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+            for (int g = 0; g < 16; g += 2) {
+                const uint32_t row = 16 * mb + 4 * (g / 4) + 2 * h + (g % 4) / 2;
+                S[row * NV + 32 * t + n] = c64{acc[mb][g], acc[mb][g + 1]};
+            }
+    }
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int m = 0; m < 32; ++m) v[m] = S[pext_c<MASK>(m) * NV + pext_c<REST>(m) * 64 + lane];
+}
+
+#define QS_MFMA_CASE(MM)                                                                  \
+    case MM:                                                                              \
+        if constexpr (__builtin_popcount(MM) <= KMAX) apply_mfma<MM>(v, A, S, lane);      \
+        break;
+
+template <int KMAX>
+__device__ __forceinline__ void mfma_dispatch(int mask, c64 (&v)[32], const float *__restrict__ A, c64 *__restrict__ S,
+                                              uint32_t lane)
+{
+    switch (mask) {
+        QS_MFMA_CASE(15) QS_MFMA_CASE(23) QS_MFMA_CASE(27) QS_MFMA_CASE(29) QS_MFMA_CASE(30) QS_MFMA_CASE(31)
+    default:
+        break;
+    }
+}
+#undef QS_MFMA_CASE
 
 // local index (within the chunk) of thread tid's register 0 in a layout:
 // thread bit j <-> local bit T[j]
@@ -378,9 +471,21 @@ __global__ __launch_bounds__(MaxThreads<R>::value) void k_block(typename AmpOf<F
                 } else if (kind == OP_DIAG_REG) {
 #pragma unroll
                     for (int m = 0; m < NR; ++m) v[m] = cmul<F, V>(M[2 * m], M[2 * m + 1], v[m]);
-                } else {   // OP_DIAG_ROW: this lane's row of the op's table in LDS
+                } else if (kind == OP_MFMA) {
+                    if constexpr (R == 5 && KMAX >= 4 && std::is_same<F, float>::value) {
+                        // the wave works in its own 16 KiB of the exchange buffer; other
+                        // waves may still be reading this phase's exchange slots there
+                        lds_barrier();
+                        const float *A = mats + ((int64_t)mlo | ((int64_t)mhi << 32));
+                        mfma_dispatch<KMAX>(variant, v, A, reinterpret_cast<c64 *>(lds_raw) + (tid >> 6) * (64 * 32),
+                                            tid & 63u);
+                    }
+                } else if (kind == OP_DIAG_ROW) {   // this lane's row of the op's table (LDS, or device memory)
                     const uint32_t row = pext_u32(tid, (uint32_t)op[1]);
-                    const V *E = reinterpret_cast<const V *>(ltab + op[3]) + (size_t)row * NR;
+                    const V *E = variant ? reinterpret_cast<const V *>(
+                                               mats + ((int64_t)(uint32_t)op[2] | ((int64_t)op[3] << 32))) +
+                                               (size_t)row * NR
+                                         : reinterpret_cast<const V *>(ltab + op[3]) + (size_t)row * NR;
 #pragma unroll
                     for (int m = 0; m < NR; ++m) {
                         const V e = E[m];

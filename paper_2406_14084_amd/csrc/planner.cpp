@@ -227,7 +227,15 @@ SetOp compose(const SetOp &e, const SetOp &o)
     return r;
 }
 
-double op_cost(bool diag, int k) { return diag ? 5.0 : 4.0 * (double)(1 << k); }
+// Relative cost of an op per amplitude (vector FMA units).  With matrix cores
+// (complex64, k >= 4) a dense op runs at twice the vector rate plus an LDS
+// round trip of the wave's amplitudes.
+double op_cost(bool diag, int k, bool mfma = false)
+{
+    if (diag) return 5.0;
+    if (mfma && k >= 4) return 2.0 * (double)(1 << k) + 8.0;
+    return 4.0 * (double)(1 << k);
+}
 
 // Convert a circuit gate to a set op over local bits (loc[j] = local bit of t[j]).
 SetOp gate_to_setop(const GateIn &G, const int *loc, int gid)
@@ -263,6 +271,7 @@ SetOp gate_to_setop(const GateIn &G, const int *loc, int gid)
 struct PhaseSched {
     int C, r, L, kmax;
     bool fuse;
+    bool mfma;      // dense ops of k >= 4 run on matrix cores
 
     // count executable ops with register set Rmask; dense ops need mask subset.
     int count(const std::vector<SetOp> &rem, uint32_t Rmask, std::vector<int> *take) const
@@ -337,11 +346,11 @@ struct PhaseSched {
                 SetOp &f = out[F];
                 uint32_t U = f.mask | o.mask;
                 int kU = popc(U);
-                double before = op_cost(f.diag, popc(f.mask)) + op_cost(o.diag, popc(o.mask));
+                double before = op_cost(f.diag, popc(f.mask), mfma) + op_cost(o.diag, popc(o.mask), mfma);
                 bool ok;
                 if (f.diag && o.diag) ok = kU <= kMaxDiagBits;
                 else if (!f.diag && o.diag) ok = (o.mask & ~f.mask) == 0;
-                else ok = (U & ~R) == 0 && kU <= kmax && op_cost(false, kU) <= before;
+                else ok = (U & ~R) == 0 && kU <= kmax && op_cost(false, kU, mfma) <= before;
                 if (ok) {
                     f = compose(f, o);
                     merged_into = F;
@@ -632,7 +641,9 @@ qs_status build_plan(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan 
     std::vector<int> rem(c->ngates);
     std::iota(rem.begin(), rem.end(), 0);
     Blocker B(gates, n);
-    PhaseSched PS{C, r, L, kf, opts.enable_fusion != 0};
+    // matrix-core ops: complex64, five register bits, whole wavefronts of threads
+    p->mfma = opts.dtype == QS_C64 && !opts.no_mfma && r == 5 && C - r >= 6;
+    PhaseSched PS{C, r, L, kf, opts.enable_fusion != 0, p->mfma};
 
     auto emit_block = [&](const std::vector<char> &inS, const std::vector<int> &take, bool last) {
         Block blk;
@@ -868,6 +879,10 @@ qs_status build_plan(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan 
     s.chunk_qubits = C;
     s.low_qubits = L;
     s.reg_qubits = r;
+    s.planner = gbg ? 2 : 0;
+    s.candidates = 1;
+    s.predicted_ms = -1.0;
+    s.predicted_heuristic_ms = -1.0;
     for (const Block &blk : p->blocks) {
         if (blk.permute_only) ++s.swap_passes;
         else ++s.blocks;
@@ -877,7 +892,11 @@ qs_status build_plan(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan 
                 ++s.ops;
                 if (op.kind == OP_DIAG) { ++s.ops_diag; s.flops_per_amp += 6.0; }
                 else if (op.kind == OP_MULTI1) { s.ops_dense[1] += op.k; s.flops_per_amp += 16.0 * op.k; }
-                else { ++s.ops_dense[op.k]; s.flops_per_amp += 8.0 * (double)(1 << op.k); }
+                else {
+                    ++s.ops_dense[op.k];
+                    s.flops_per_amp += 8.0 * (double)(1 << op.k);
+                    if (p->mfma && op.k >= 4) ++s.ops_mfma;
+                }
             }
         }
     }
@@ -987,6 +1006,8 @@ void encode_plan(Plan *p)
         for (int b = 0; b < C; ++b) w.push_back(blk.P_out[b]);
         std::vector<int32_t> tab;   // per-lane data of diagonal ops, staged in LDS by the kernel
         const bool c64 = (p->dtype == QS_C64);
+        // LDS left beside the chunk's exchange buffer (words); larger tables go to device memory
+        const size_t tab_cap = (160u * 1024u - ((size_t)(c64 ? 8 : 16) << C)) / 4;
         for (size_t ph = 0; ph < blk.phases.size(); ++ph) {
             const Phase &P = blk.phases[ph];
             uint64_t swz = (ph > 0) ? choose_swizzle(blk.phases[ph - 1].lay, P.lay, C, r) : 0;
@@ -1031,6 +1052,29 @@ void encode_plan(Plan *p)
             }
             for (const Op &op : P.ops) {
                 int64_t moff = (int64_t)p->h_mats.size();
+                if (op.kind == OP_DENSE && p->mfma && op.k >= 4) {
+                    // Matrix-core form: the real embedding [[Re U, -Im U], [Im U, Re U]] of U,
+                    // stored in the order the kernel feeds the 32x32x2 FP32 product: block mb
+                    // of 32 output rows, step s, lane.  Output row mm = 2 i + (0 re | 1 im) of
+                    // element i; at step s lane (m, h) = (lane % 32, lane / 32) holds the
+                    // coefficient of part (s % 2) of input element 2 (s / 2) + h.
+                    const int D = 1 << op.k, nmb = D / 16;
+                    for (int mb = 0; mb < nmb; ++mb)
+                        for (int s = 0; s < D; ++s)
+                            for (int lane = 0; lane < 64; ++lane) {
+                                const int mm = 32 * mb + lane % 32, row = mm / 2, po = mm % 2;
+                                const int col = 2 * (s / 2) + lane / 32, pi = s % 2;
+                                const cplx u = op.m[(size_t)row * D + col];
+                                double a = (po == pi) ? u.real() : u.imag();
+                                if (po == 0 && pi == 1) a = -a;
+                                p->h_mats.push_back(a);
+                            }
+                    w.push_back(OP_MFMA | (op.regmask << 8) | (op.k << 16));
+                    w.push_back((int32_t)(uint32_t)(moff & 0xffffffff));
+                    w.push_back((int32_t)(uint32_t)(moff >> 32));
+                    w.push_back(0);
+                    continue;
+                }
                 if (op.kind == OP_DENSE || op.kind == OP_MULTI1) {
                     for (const cplx &z : op.m) { p->h_mats.push_back(z.real()); p->h_mats.push_back(z.imag()); }
                     w.push_back(op.kind | (op.regmask << 8) | (op.k << 16));
@@ -1062,6 +1106,7 @@ void encode_plan(Plan *p)
                     return op.m[idx];
                 };
                 const int rows = 1 << kt;
+                bool global_tab = false;      // the per-row table does not fit beside the chunk in LDS
                 if (sign) {
                     std::vector<int32_t> masks(rows, 0);
                     for (int row = 0; row < rows; ++row)
@@ -1072,14 +1117,17 @@ void encode_plan(Plan *p)
                         w.push_back(0);
                         w.push_back(0);
                         w.push_back(masks[0]);
-                    } else {
+                        continue;
+                    }
+                    if (tab.size() + (size_t)rows <= tab_cap) {
                         w.push_back(OP_SIGN_ROW | (op.k << 16));
                         w.push_back((int32_t)tmask);
                         w.push_back(0);
                         w.push_back((int32_t)tab.size());
                         tab.insert(tab.end(), masks.begin(), masks.end());
+                        continue;
                     }
-                    continue;
+                    global_tab = true;        // as a +-1 diagonal read from device memory
                 }
                 if (kt == 0) {
                     for (int m = 0; m < NR; ++m) {
@@ -1091,6 +1139,21 @@ void encode_plan(Plan *p)
                     w.push_back((int32_t)(uint32_t)(moff & 0xffffffff));
                     w.push_back((int32_t)(uint32_t)(moff >> 32));
                     w.push_back(0);
+                    continue;
+                }
+                const size_t row_words = (size_t)NR * (c64 ? 2 : 4);
+                if (global_tab || ((tab.size() + 3) & ~(size_t)3) + (size_t)rows * row_words > tab_cap) {
+                    // table in device memory (variant 1): rows of 2^r entries, interleaved re/im
+                    for (int row = 0; row < rows; ++row)
+                        for (int m = 0; m < NR; ++m) {
+                            cplx z = entry(row, m);
+                            p->h_mats.push_back(z.real());
+                            p->h_mats.push_back(z.imag());
+                        }
+                    w.push_back(OP_DIAG_ROW | (1 << 8) | (op.k << 16));
+                    w.push_back((int32_t)tmask);
+                    w.push_back((int32_t)(uint32_t)(moff & 0xffffffff));
+                    w.push_back((int32_t)(uint32_t)(moff >> 32));
                     continue;
                 }
                 while (tab.size() % 4) tab.push_back(0);     // 16-byte aligned rows

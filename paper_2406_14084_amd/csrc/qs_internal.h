@@ -32,7 +32,8 @@ enum OpKind {
     OP_DIAG_ROW = 3,   //   some bits are thread bits: 2^kt rows of 2^r entries, row = pext(tid, tmask)
     OP_SIGN_REG = 4,   //   entries all +-1, bits in registers: bit m of a mask negates register m
     OP_SIGN_ROW = 5,   //   entries all +-1 with thread bits: one such mask per row
-    OP_MULTI1 = 6      // one 2x2 gate on each register bit of regmask (they commute), ascending bit order
+    OP_MULTI1 = 6,     // one 2x2 gate on each register bit of regmask (they commute), ascending bit order
+    OP_MFMA = 7        // encoding of a complex64 dense op of k >= 4 register bits run on matrix cores
 };
 
 struct Op {
@@ -70,6 +71,7 @@ struct Plan {
     qs_dtype dtype = QS_C128;
     int C = 12, L = 4, r = 4;
     int kmax = 5;
+    bool mfma = false;                  // complex64 dense ops of k >= 4 are encoded as OP_MFMA
     std::vector<Block> blocks;          // steps, in order (swap passes are blocks with permute_only)
     std::vector<std::vector<int>> layouts;  // l2p before each step, plus the final one
     int ngates = 0;
@@ -97,8 +99,10 @@ qs_status build_swap_plan(int n, qs_dtype dtype, int s, const int *a, const int 
 void encode_plan(Plan *p);
 // Text dump.
 std::string dump_plan(const Plan &p);
-// Block features for the cost model (48 per block).
+// Block features for the cost model (48 per step, swap passes included).
 void block_features(const Plan &p, std::vector<float> *out);
+// Learned planner: candidate plans ranked by the cost model (opts->cost_model).
+qs_status build_plan_learned(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan *p, std::string *err);
 
 // ---------------------------------------------------------------------------
 // Program encoding read by the blocked kernel (int32 words per block):
@@ -119,8 +123,11 @@ void block_features(const Plan &p, std::vector<float> *out);
 //       DENSE   : variant = register mask; w1,w2 = matrix offset (scalars, lo/hi)
 //       MULTI1  : variant = register mask; w1,w2 = offset of one 2x2 matrix per set bit, ascending
 //       DIAG_REG: w1,w2 = offset of 2^r entries (register order)
-//       DIAG_ROW: w1 = tmask (thread-index bits of the row); w3 = word offset in the table of
-//                 2^kt rows of 2^r entries (complex128: 4 words each, complex64: 2)
+//       DIAG_ROW: w1 = tmask (thread-index bits of the row); variant 0: w3 = word offset in the
+//                 table of 2^kt rows of 2^r entries (complex128: 4 words each, complex64: 2);
+//                 variant 1 (table too large for LDS): w2,w3 = offset of the rows in the matrices
+//       MFMA    : variant = register mask (k = 4, 5 of r = 5); w1,w2 = offset of the real-embedded
+//                 matrix in matrix-core operand order (complex64 only)
 //       SIGN_REG: w3 = mask over registers (bit m set: negate register m)
 //       SIGN_ROW: w1 = tmask; w3 = word offset in the table of 2^kt row masks
 // The table (per-lane data of diagonal ops) is copied into LDS, after the
@@ -165,6 +172,8 @@ hipError_t launch_probs(qs_state *st, double *out);
 hipError_t launch_expect(qs_state *st, int nterms, const qs_pauli *terms, double *partials, int nparts);
 int expect_partials(int n);
 hipError_t launch_block(qs_state *st, const Plan &p, int b);
+hipStream_t costmodel_stream(const qs_costmodel *m);
+int costmodel_device(const qs_costmodel *m);
 hipError_t launch_block_prog(qs_state *st, int r, int C, const int *d_prog, const void *d_mats, size_t tab_bytes,
                              int kmax_dense);
 }

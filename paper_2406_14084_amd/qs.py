@@ -34,7 +34,7 @@ class Circuit_C(C.Structure):
 class PlanOpts_C(C.Structure):
     _fields_ = [("chunk_qubits", C.c_int), ("low_qubits", C.c_int), ("enable_swaps", C.c_int),
                 ("enable_fusion", C.c_int), ("planner", C.c_int), ("cost_model", C.c_void_p),
-                ("dtype", C.c_int), ("reg_qubits", C.c_int)]
+                ("dtype", C.c_int), ("reg_qubits", C.c_int), ("no_mfma", C.c_int)]
 
 
 class Pauli_C(C.Structure):
@@ -45,7 +45,9 @@ class PlanStats_C(C.Structure):
     _fields_ = [("n", C.c_int), ("dtype", C.c_int), ("gates", C.c_int), ("blocks", C.c_int),
                 ("swap_passes", C.c_int), ("ops", C.c_int), ("ops_dense", C.c_int * 6), ("ops_diag", C.c_int),
                 ("phases", C.c_int), ("chunk_qubits", C.c_int), ("low_qubits", C.c_int), ("reg_qubits", C.c_int),
-                ("flops_per_amp", C.c_double), ("hbm_bytes", C.c_double), ("plan_seconds", C.c_double)]
+                ("flops_per_amp", C.c_double), ("hbm_bytes", C.c_double), ("plan_seconds", C.c_double),
+                ("planner", C.c_int), ("candidates", C.c_int), ("predicted_ms", C.c_double),
+                ("predicted_heuristic_ms", C.c_double), ("ops_mfma", C.c_int)]
 
 
 class QaoaInst_C(C.Structure):
@@ -228,13 +230,14 @@ class Plan:
     .n and .arrays())."""
 
     def __init__(self, circuit, kmax=5, dtype="c128", chunk_qubits=0, low_qubits=0, swaps=True, fusion=True,
-                 planner=0, cost_model=None, reg_qubits=0):
+                 planner=0, cost_model=None, reg_qubits=0, mfma=True):
         k, t, m = circuit.arrays()
         self._keep = (k, t, m)
         circ = Circuit_C(circuit.n, len(k), _ip(k), _ip(t), _dp(m))
         opts = PlanOpts_C(chunk_qubits, low_qubits, int(swaps), int(fusion), planner,
                           cost_model.h if cost_model is not None else None,
-                          QS_C64 if dtype in ("c64", "complex64", QS_C64) else QS_C128, reg_qubits)
+                          QS_C64 if dtype in ("c64", "complex64", QS_C64) else QS_C128, reg_qubits,
+                          0 if mfma else 1)
         h = C.c_void_p()
         check(lib().qs_fuse(C.byref(circ), kmax, C.byref(opts), C.byref(h)))
         self.h = h
@@ -296,6 +299,14 @@ class Plan:
                                     _dp(m), nm.value, None))
         return w, o[:ns.value], r.value, Cc.value, m
 
+    def features(self):
+        """Cost-model features of every step (gate blocks and swap passes), (steps, 48) float32."""
+        nb = C.c_int()
+        check(lib().qs_plan_block_features(self.h, None, 0, C.byref(nb)))
+        f = np.zeros((nb.value, COST_FEATURES), dtype=np.float32)
+        check(lib().qs_plan_block_features(self.h, f.ctypes.data_as(C.POINTER(C.c_float)), nb.value, C.byref(nb)))
+        return f
+
     def nsteps(self):
         ns = C.c_int()
         perm = (C.c_int * self.n)()
@@ -311,6 +322,76 @@ class Plan:
             check(lib().qs_plan_layout(self.h, s, perm, None))
             out.append(list(perm))
         return out
+
+
+COST_FEATURES = 48
+COST_PARAMS = 128 * 48 + 128 + 128 * 128 + 128 + 128 + 1
+
+
+class CostModel:
+    """The plan cost model (48 -> 128 -> 128 -> 1 FP32 MLP) on the GPU; its
+    forward, backward and Adam steps run in the library's own kernels.
+    Parameters are a flat float32 vector: W1 (128x48), b1, W2 (128x128), b2,
+    W3 (1x128), b3, row-major."""
+
+    def __init__(self, seed=0, stream=None):
+        self._torch = _torch()
+        self._stream = stream
+        h = C.c_void_p()
+        check(lib().qs_costmodel_create(int(seed), _stream_ptr(stream), C.byref(h)))
+        self.h = h
+
+    def get_params(self):
+        p = np.zeros(COST_PARAMS, dtype=np.float32)
+        check(lib().qs_costmodel_get_params(self.h, p.ctypes.data_as(C.POINTER(C.c_float))))
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        if p.size != COST_PARAMS:
+            raise ValueError("expected %d parameters" % COST_PARAMS)
+        check(lib().qs_costmodel_set_params(self.h, p.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def get_grads(self):
+        g = np.zeros(COST_PARAMS, dtype=np.float32)
+        check(lib().qs_costmodel_get_grads(self.h, g.ctypes.data_as(C.POINTER(C.c_float))))
+        return g
+
+    def _dev(self, a, dtype):
+        torch = self._torch
+        t = torch.as_tensor(a, dtype=dtype)
+        return t.to("cuda").contiguous()
+
+    def train_step(self, X, y, lr=1e-3, want_loss=True):
+        """One Adam step on a minibatch (rows <= 1024); X, y: numpy or cuda tensors."""
+        torch = self._torch
+        Xd = X if isinstance(X, torch.Tensor) and X.is_cuda else self._dev(X, torch.float32)
+        yd = y if isinstance(y, torch.Tensor) and y.is_cuda else self._dev(y, torch.float32)
+        loss = C.c_float()
+        check(lib().qs_costmodel_train_step(self.h, C.c_void_p(Xd.data_ptr()), C.c_void_p(yd.data_ptr()),
+                                            int(Xd.shape[0]), float(lr), C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def predict(self, X):
+        """Model outputs for the rows of X (float32 cuda tensor returned)."""
+        torch = self._torch
+        Xd = X if isinstance(X, torch.Tensor) and X.is_cuda else self._dev(X, torch.float32)
+        out = torch.empty(int(Xd.shape[0]), dtype=torch.float32, device="cuda")
+        check(lib().qs_costmodel_predict(self.h, C.c_void_p(Xd.data_ptr()), C.c_void_p(out.data_ptr()),
+                                         int(Xd.shape[0])))
+        (self._stream or torch.cuda.current_stream()).synchronize()
+        return out
+
+    def close(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            lib().qs_costmodel_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class QaoaBatch:

@@ -147,3 +147,32 @@ def test_c64_vs_c128_32q(torch):
     rig, typ = bound_for(p32)
     say("32q: ||d||2 = %.3e max|d| = %.3e 1-F = %.3e bound %.3e typical %.3e" % (d2, dmax, 1 - fid, rig, typ))
     assert d2 <= rig
+
+
+@pytest.mark.parametrize("n,seed,chunk", [(14, 21, 0), (18, 22, 11), (20, 23, 12)])
+def test_c64_matrix_core_ops_vs_oracle(torch, n, seed, chunk):
+    """Dense ops of 4-5 qubits on the matrix cores (FP32 products, FP32
+    accumulation): within the same rigorous bound as the vector path (the
+    inner-product bound holds for any summation order), and close to the
+    vector-FMA run of the same circuit."""
+    rng = np.random.default_rng(seed)
+    c = I.random_dense(n, 100, seed, kmax=3)
+    for _ in range(12):
+        tg = tuple(int(x) for x in rng.choice(n, 5, replace=False))
+        c.add("U5", tg, I.g_haar(rng, 32))
+    want = sim.run(c)
+    out = {}
+    for mf in (True, False):
+        p = qs.Plan(c, kmax=5, dtype="c64", chunk_qubits=chunk, mfma=mf)
+        assert (p.stats()["ops_mfma"] > 0) == mf
+        st = qs.State(n, "c64")
+        st.init_zero()
+        st.apply_plan(p)
+        got = st.numpy().astype(np.complex128)
+        d2 = float(np.linalg.norm(got - want))
+        rig, typ = bound_for(p)
+        say("mfma=%s n=%d ||d||2 = %.3e bound %.3e (typical %.3e) mfma ops %d"
+            % (mf, n, d2, rig, typ, p.stats()["ops_mfma"]))
+        assert d2 <= rig
+        out[mf] = (got, rig)
+    assert float(np.linalg.norm(out[True][0] - out[False][0])) <= out[True][1] + out[False][1]

@@ -64,7 +64,55 @@ def _swz(l, swlo, swhi):
     return l ^ f
 
 
-def replay_block(psi, w, n, R, mats):
+def _replay_mfma(v, mask, k, A, R, tb):
+    """The wave algorithm of the matrix-core op: registers -> the wave's LDS
+    region S[element][vector] -> B operands -> 32x32x2 products with the
+    documented operand layouts (A[i][k], B[k][j] in lane i|j + 32 k; D[i][j] in
+    lane j + 32 ((i / 4) % 2), accumulator 4 (i / 8) + i % 4) -> S -> registers."""
+    assert R == 5 and k in (4, 5) and bin(mask).count("1") == k and mask < 32
+    nth = 1 << tb
+    assert nth % 64 == 0
+    D, NV, NMB = 1 << k, 64 << (5 - k), (1 << k) // 16
+    A = np.asarray(A[:NMB * D * 64], dtype=np.float64).reshape(NMB, D, 64)
+    nw = v.shape[0]
+    vw = v.reshape(nw, nth // 64, 64, 32)
+    S = np.zeros((nw, nth // 64, D, NV), dtype=np.complex128)
+    rest = 31 & ~mask
+    for m in range(32):
+        c, e = _pext(m, mask), _pext(m, rest)
+        S[:, :, c, 64 * e:64 * e + 64] = vw[:, :, :, m]
+    for t in range(NV // 32):
+        # B operand of step s, lane (n, h): part s % 2 of element 2 (s // 2) + h of vector 32 t + n
+        B = np.zeros((nw, nth // 64, D, 64))
+        for s in range(D):
+            for h in (0, 1):
+                x = S[:, :, 2 * (s // 2) + h, 32 * t:32 * t + 32]
+                B[:, :, s, 32 * h:32 * h + 32] = x.real if s % 2 == 0 else x.imag
+        for mb in range(NMB):
+            acc = np.zeros((nw, nth // 64, 32, 32))
+            for s in range(D):
+                Aop = np.stack([A[mb, s, 0:32], A[mb, s, 32:64]], axis=1)                 # A[i][kk]
+                Bop = np.stack([B[:, :, s, 0:32], B[:, :, s, 32:64]], axis=2)             # B[kk][j]
+                acc += np.einsum("ik,wvkj->wvij", Aop, Bop)
+            # D in lanes/accumulators, then as the kernel stores it: accumulators g, g + 1 of
+            # lane (n, h) -> element 16 mb + 4 (g / 4) + 2 h + (g % 4) / 2 of vector 32 t + n
+            lanes = np.zeros((nw, nth // 64, 64, 16))
+            for i in range(32):
+                for j in range(32):
+                    lanes[:, :, j + 32 * ((i // 4) % 2), 4 * (i // 8) + i % 4] = acc[:, :, i, j]
+            for lane in range(64):
+                n_, h = lane % 32, lane // 32
+                for g in range(0, 16, 2):
+                    row = 16 * mb + 4 * (g // 4) + 2 * h + (g % 4) // 2
+                    S[:, :, row, 32 * t + n_] = lanes[:, :, lane, g] + 1j * lanes[:, :, lane, g + 1]
+    out = np.empty_like(vw)
+    for m in range(32):
+        c, e = _pext(m, mask), _pext(m, rest)
+        out[:, :, :, m] = S[:, :, c, 64 * e:64 * e + 64]
+    return out.reshape(v.shape)
+
+
+def replay_block(psi, w, n, R, mats, c64=False):
     nph, C = int(w[0]), int(w[1])
     assert int(w[2]) == R
     tb = C - R
@@ -83,7 +131,7 @@ def replay_block(psi, w, n, R, mats):
     tab_off, tab_words = int(w[4]), int(w[5])
     assert tab_off % 4 == 0 and (tab_words == 0 or tab_off >= ph)
     # the table plus the exchange buffer must fit the 160 KiB of LDS
-    assert (16 << C) + 4 * tab_words <= 160 * 1024
+    assert ((8 if c64 else 16) << C) + 4 * tab_words <= 160 * 1024
 
     def layout(at):
         Rb = [int(x) for x in w[at + PHASE_HDR:at + PHASE_HDR + R]]
@@ -118,7 +166,7 @@ def replay_block(psi, w, n, R, mats):
             rs = rt[:, None] ^ rl[None, :]
             # the kernel forms the same slots from the program's exchange block
             X = ph + PHASE_HDR + C
-            ab = 16
+            ab = 8 if c64 else 16
             xw = [int(x) for x in w[X:X + tb]]
             xr = [int(x) for x in w[X + tb:X + 2 * tb]]
             wo = np.array([int(x) for x in w[X + 2 * tb:X + 2 * tb + NR]])
@@ -171,14 +219,24 @@ def replay_block(psi, w, n, R, mats):
             elif kind == 2:       # register diagonal: uniform entry per register
                 E = mats[moff:moff + 2 * NR].view(np.complex128)
                 v = v * E[None, None, :]
-            elif kind == 3:       # per-row diagonal from the LDS table: row = pext(tid, tmask)
+            elif kind == 3:       # per-row diagonal: row = pext(tid, tmask)
                 tmask = int(w[op + 1])
                 row = _pext(tid, tmask)
                 kt = bin(tmask).count("1")
-                a = tab_off + int(w[op + 3])
-                assert a % 4 == 0 and int(w[op + 3]) + 4 * NR * (1 << kt) <= tab_words
-                E = np.ascontiguousarray(w[a:a + 4 * NR * (1 << kt)]).view(np.complex128).reshape(1 << kt, NR)
+                if variant == 1:  # rows in device memory (table too large for LDS)
+                    goff = int(np.uint32(w[op + 2])) | (int(w[op + 3]) << 32)
+                    E = mats[goff:goff + 2 * NR * (1 << kt)].view(np.complex128).reshape(1 << kt, NR)
+                else:             # rows in the LDS table
+                    assert variant == 0
+                    wpe = 2 if c64 else 4
+                    a = tab_off + int(w[op + 3])
+                    assert a % 4 == 0 and int(w[op + 3]) + wpe * NR * (1 << kt) <= tab_words
+                    raw = np.ascontiguousarray(w[a:a + wpe * NR * (1 << kt)])
+                    E = (raw.view(np.complex64).astype(np.complex128) if c64 else raw.view(np.complex128))
+                    E = E.reshape(1 << kt, NR)
                 v = v * E[row][None, :, :]
+            elif kind == 7:       # complex64 dense op on matrix cores, emulated lane by lane
+                v = _replay_mfma(v, variant, k, mats[moff:], R, tb)
             elif kind == 4:       # +-1 on registers
                 s = int(np.uint32(w[op + 3]))
                 sg = np.array([-1.0 if (s >> m) & 1 else 1.0 for m in range(NR)])
@@ -220,8 +278,9 @@ def replay_plan(plan, n):
     w, offs, R, C, mats = plan.program()
     psi = np.zeros(1 << n, dtype=np.complex128)
     psi[0] = 1
+    c64 = plan.stats()["dtype"] == 1
     for o in offs:
-        psi = replay_block(psi, w[o:], n, R, mats)
+        psi = replay_block(psi, w[o:], n, R, mats, c64)
     return psi
 
 
@@ -332,3 +391,76 @@ def test_exchange_swizzle_spreads_lanes():
             pT = T
             ph = ph + PHASE_HDR + C + 2 * (C - R) + 2 * (1 << R) + OP_WORDS * int(w[ph])
     assert total > 0 and bad == 0, (bad, total)
+
+
+def _diag_row_variants(p):
+    out = set()
+    w, offs, R, C, mats = p.program()
+    for o in offs:
+        nph = int(w[o]); ph = o + PROG_HDR + 2 * C
+        for _ in range(nph):
+            nops = int(w[ph]); op = ph + PHASE_HDR + C + 2 * (C - R) + 2 * (1 << R)
+            for _ in range(nops):
+                if int(w[op]) & 0xff == 3:
+                    out.add((int(w[op]) >> 8) & 0xff)
+                op += OP_WORDS
+            ph = op
+    return out
+
+
+def _five_qubit_circuit(n, seed, count=10):
+    rng = np.random.default_rng(seed)
+    c = I.random_dense(n, 60, seed, kmax=3)
+    for _ in range(count):
+        tg = tuple(int(x) for x in rng.choice(n, 5, replace=False))
+        c.add("U5", tg, I.g_haar(rng, 32))
+    return c
+
+
+@pytest.mark.parametrize("cfg", [
+    dict(n=13, seed=1), dict(n=14, seed=2, chunk_qubits=11), dict(n=15, seed=3, chunk_qubits=12),
+    dict(n=16, seed=4, swaps=False),
+])
+def test_replay_complex64_matrix_core_ops(cfg):
+    """Complex64 plans encode dense ops of 4-5 qubits for the matrix cores;
+    the lane-by-lane emulation of the kernel's algorithm (with the program's
+    FP64 copy of the operands) reproduces the oracle; an index mistake in the
+    operand or result layouts would show as O(1) errors."""
+    cfg = dict(cfg)
+    n, seed = cfg.pop("n"), cfg.pop("seed")
+    c = _five_qubit_circuit(n, seed)
+    p = qs.Plan(c, kmax=5, dtype="c64", **cfg)
+    s = p.stats()
+    assert s["ops_mfma"] > 0 and 7 in _op_kinds(p)
+    assert s["ops_mfma"] <= s["ops_dense"][4] + s["ops_dense"][5]
+    # complex64 LDS tables of diagonals hold FP32 entries (rounded once): ~1e-9 here
+    assert np.max(np.abs(replay_plan(p, n) - sim.run(c))) <= 1e-7
+    q = qs.Plan(c, kmax=5, dtype="c64", mfma=False, **cfg)
+    assert q.stats()["ops_mfma"] == 0 and 7 not in _op_kinds(q)
+
+
+def test_matrix_core_ops_need_full_waves():
+    """No matrix-core op where a workgroup has less than a wavefront of threads
+    or the plan is complex128."""
+    c = _five_qubit_circuit(12, 5)
+    assert qs.Plan(c, kmax=5, dtype="c64", chunk_qubits=10).stats()["ops_mfma"] == 0
+    assert qs.Plan(c, kmax=5, dtype="c128").stats()["ops_mfma"] == 0
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_replay_large_diagonal_tables_spill(dtype):
+    """Diagonals merged over many thread bits make row tables larger than the
+    LDS left beside a 13-qubit chunk; those tables are read from device memory
+    (DIAG_ROW variant 1) and the replay still matches the oracle."""
+    n = 16
+    rng = np.random.default_rng(7)
+    c = I.Circuit(n)
+    for _ in range(40):
+        tg = tuple(int(x) for x in rng.choice(n, 4, replace=False))
+        c.add("D4", tg, np.diag(np.exp(1j * rng.uniform(0, 6.3, 16))))
+        c.add("H", (int(rng.integers(n)),), I.g_h())
+    p = qs.Plan(c, kmax=5, chunk_qubits=13, reg_qubits=3, dtype=dtype)
+    # complex64 tables are half the size and fit beside the (half-size) chunk
+    assert _diag_row_variants(p) == ({0, 1} if dtype == "c128" else {0})
+    tol = 1e-7 if dtype == "c64" else 1e-12
+    assert np.max(np.abs(replay_plan(p, n) - sim.run(c))) <= tol

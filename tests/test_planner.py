@@ -165,3 +165,35 @@ def test_fuse_rejects_bad_gates(bad):
     with pytest.raises(qs.QSError) as e:
         qs.Plan(Raw(), kmax=3)
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("gen,opts", [
+    (lambda: I.random_su4(n=24, depth=10, seed=3), dict(kmax=5)),
+    (lambda: I.random_dense(22, 200, 8, kmax=3), dict(kmax=4, reg_qubits=3)),
+    (lambda: I.qft(20), dict(kmax=3, chunk_qubits=11, low_qubits=5)),
+    (lambda: I.layered_rotations(n=26, layers=6, seed=5), dict(kmax=5, dtype="c64")),
+])
+def test_block_features_consistent(gen, opts):
+    """The cost model's step features agree with the plan they describe:
+    one row per step, the swap-pass flag, and op counts and flops that add
+    up to the plan's own statistics."""
+    p = qs.Plan(gen(), **opts)
+    f = p.features()
+    s = p.stats()
+    assert f.shape == (p.nsteps(), qs.COST_FEATURES) and np.all(np.isfinite(f))
+    assert int(round(f[:, 0].sum())) == s["swap_passes"]
+    assert np.all(f[:, 1] == (1.0 if opts.get("dtype") == "c64" else 0.0))
+    cnt = lambda col, scale: int(round(float((f[:, col].astype(np.float64) * scale).sum())))
+    for k in range(2, 6):
+        assert cnt(10 + k, 8) == s["ops_dense"][k], k
+    assert cnt(11, 8) + cnt(21, 16) == s["ops_dense"][1]
+    assert cnt(16, 8) + cnt(17, 8) + cnt(18, 8) + cnt(19, 8) == s["ops_diag"]
+    sign_ops = cnt(18, 8) + cnt(19, 8)
+    # stats price every diagonal at 6 flops per amplitude; +-1 diagonals cost none in the features
+    assert abs(float((f[:, 22].astype(np.float64) * 256).sum()) + 6 * sign_ops - s["flops_per_amp"]) < 1e-3 * s["flops_per_amp"] + 1
+
+
+def test_learned_planner_needs_model():
+    with pytest.raises(qs.QSError) as e:
+        qs.Plan(I.random_su4(n=12, depth=4, seed=1), kmax=5, planner=1)
+    assert e.value.code == -1
