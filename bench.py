@@ -8,14 +8,21 @@ on the GPU through the C ABI.  The plan is built once beforehand (its host
 time is reported as plan_seconds, like the paper's separate optimiser time).
 
 Printed: one JSON line with gate-applications/s, the dominant kernel's
-roofline figures (per-launch device time from events around every launch),
-the gate-by-gate path's throughput on the same circuit, and the CPU oracle
-timed on a bounded sample of the same workload.
+roofline figures (per-launch device time from events around every launch;
+HBM traffic per launch from the committed hardware-counter summary when it
+was taken on the current kernel and planner sources), the gate-by-gate
+path's throughput on the same circuit, the CPU oracle timed on a bounded
+sample of the same workload, and the variants compared with the plain fused
+path: complex64 with matrix-core ops (32 qubits), 512 batched QAOA
+instances in one launch vs 512 launches, and (with --learned) the learned
+planner on a 33-qubit complex128 circuit.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -28,6 +35,37 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0        # MI355X published HBM3E bandwidth
 FP64_PEAK_TFLOPS = 78.6      # MI355X published FP64 vector (= matrix) rate
 WORKLOAD = dict(n=30, depth=40, seed=30002, kmax=5)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_block_traffic_u3cz30.txt")
+TRAFFIC_SOURCES = ("paper_2406_14084_amd/csrc/k_block.hip", "paper_2406_14084_amd/csrc/planner.cpp")
+
+
+def sources_sha256():
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(n):
+    """HBM bytes per gate-block launch from the counter summary (FETCH_SIZE and
+    WRITE_SIZE per dispatch, each scaled by the same counter's reading for a
+    copy of known size); None if absent, for another size, or taken on other
+    kernel/planner sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    try:
+        if kv.get("sources_sha256") != sources_sha256() or int(kv["n"]) != n:
+            return None
+        return float(kv["traffic_bytes_per_gate_block"])
+    except (KeyError, ValueError):
+        return None
 
 
 def log(*a):
@@ -59,6 +97,87 @@ def cpu_baseline(circ, max_gates, budget_s):
             "seconds": dt}
 
 
+def _ms(torch, fn, reps=2):
+    best = float("inf")
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b))
+    return best
+
+
+def bench_c64(torch, I, qs):
+    """32-qubit complex64 U3 + CX depth 60: matrix-core ops vs vector FMA only;
+    the rigorous state-error bound of the plan beside it."""
+    n = 32
+    c = I.random_u3_2q(n=n, depth=60, seed=32003, two="CX")
+    st = qs.State(n, "c64")
+    res = {"workload": "random U3 + CX(random perfect matching), 32 qubits, depth 60, seed 32003, complex64",
+           "gates": len(c)}
+    u = 2.0 ** -24
+    gam = lambda m: m * u / (1 - m * u)
+    for name, mf in (("mfma", True), ("vector", False)):
+        p = qs.Plan(c, kmax=5, dtype="c64", mfma=mf)
+        s = p.stats()
+        ms = _ms(torch, lambda: (st.init_zero(), st.apply_plan(p)))
+        bound = sum(s["ops_dense"][k] * (math.sqrt(2) * gam(2 ** (k + 1)) + u) * 2 ** (k / 2) for k in range(1, 6)) \
+            + s["ops_diag"] * (math.sqrt(2) * gam(2) + u)
+        res[name] = {"ms": round(ms, 2), "gate_applications_per_s": round(len(c) / (ms * 1e-3), 1),
+                     "ops_mfma": s["ops_mfma"], "ops_dense": s["ops_dense"], "blocks": s["blocks"],
+                     "swap_passes": s["swap_passes"], "flops_per_amp": s["flops_per_amp"],
+                     "state_error_bound_l2": bound}
+        log("complex64 32q %s: %.1f ms" % (name, ms))
+    res["speedup_mfma_vs_vector"] = round(res["vector"]["ms"] / res["mfma"]["ms"], 3)
+    del st
+    return res
+
+
+def bench_qaoa(torch, I, qs):
+    """512 MaxCut QAOA instances (3-regular, 10-20 qubits, p = 4, complex64):
+    one graph-captured persistent launch vs 512 sequential launches."""
+    insts = I.qaoa_batch(count=512, p=4, seed=512004)
+    b = qs.QaoaBatch(insts, "c64")
+    choice, tune_ms = b.autotune()
+    b.run(graph=True)
+    batched = _ms(torch, lambda: b.run(graph=True), reps=3)
+    seq = _ms(torch, lambda: b.run_sequential(), reps=3)
+    err = b.error()
+    gates = sum(len(q.circuit()) for q in insts)
+    log("qaoa batch: %.2f ms batched, %.2f ms sequential" % (batched, seq))
+    return {"workload": "512 QAOA MaxCut instances, random 3-regular graphs, 10-20 qubits, p=4, seed 512004, complex64",
+            "batched_ms": round(batched, 3), "sequential_ms": round(seq, 3),
+            "speedup_batched_vs_sequential": round(seq / batched, 2), "autotune_choice": choice,
+            "gate_applications_per_s_batched": round(gates / (batched * 1e-3), 1), "spin_error_flag": err}
+
+
+def bench_learned(torch, I, qs):
+    """33-qubit complex128 (128 GiB) depth-60 Haar SU(4) circuit: learned vs heuristic planner."""
+    from paper_2406_14084_amd import costmodel
+    n = 33
+    c = I.random_su4(n=n, depth=60, seed=33005)
+    model = costmodel.load_default()
+    ph = qs.Plan(c, kmax=5)
+    pl = qs.Plan(c, kmax=5, planner=1, cost_model=model)
+    pp = qs.Plan(c, kmax=5, planner=3)
+    st = qs.State(n, "c128")
+    th = _ms(torch, lambda: (st.init_zero(), st.apply_plan(ph)), reps=1)
+    tl = _ms(torch, lambda: (st.init_zero(), st.apply_plan(pl)), reps=1)
+    tp = _ms(torch, lambda: (st.init_zero(), st.apply_plan(pp)), reps=1)
+    s, sp = pl.stats(), pp.stats()
+    log("learned 33q: heuristic %.0f ms, learned %.0f ms, fewest passes %.0f ms" % (th, tl, tp))
+    del st
+    keys = ("planner", "chunk_qubits", "reg_qubits", "low_qubits", "blocks", "swap_passes", "candidates",
+            "predicted_ms", "predicted_heuristic_ms")
+    return {"workload": "Haar SU(4) on random pairs, 33 qubits, depth 60, seed 33005, complex128",
+            "heuristic_ms": round(th, 1), "learned_ms": round(tl, 1), "fewest_passes_ms": round(tp, 1),
+            "gain_vs_heuristic": round((th - tl) / th, 4), "gain_vs_fewest_passes": round((tp - tl) / tp, 4),
+            "learned_choice": {k: s[k] for k in keys}, "fewest_passes_choice": {k: sp[k] for k in keys}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,6 +189,8 @@ def main():
     ap.add_argument("--n", type=int, default=WORKLOAD["n"])
     ap.add_argument("--chunk", type=int, default=0, help="chunk qubits C (0 = library default)")
     ap.add_argument("--reg-qubits", type=int, default=0, help="register qubits per thread r (0 = default)")
+    ap.add_argument("--no-variants", action="store_true", help="skip the complex64 and batched-QAOA comparisons")
+    ap.add_argument("--learned", action="store_true", help="also compare the learned planner at 33 qubits (128 GiB)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no collectives); use --gpus 1", file=sys.stderr)
@@ -134,10 +255,14 @@ def main():
     ach_tf = flops_per_launch / (avg_ms * 1e-3) / 1e12
     if t_alu > t_hbm:
         roof = {"bound": "alu", "achieved": round(ach_tf, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(ach_tf / FP64_PEAK_TFLOPS, 4), "traffic": None}
+                "frac": round(ach_tf / FP64_PEAK_TFLOPS, 4)}
     else:
         roof = {"bound": "hbm", "achieved": round(ach_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach_gbs / HBM_PEAK_GBS, 4), "traffic": None}
+                "frac": round(ach_gbs / HBM_PEAK_GBS, 4)}
+    tr = measured_traffic(n) if (args.chunk == 0 and args.reg_qubits == 0) else None
+    roof["traffic"] = tr
+    if tr is not None:
+        roof["traffic_over_algorithmic"] = round(tr / pass_bytes, 4)
     roof["kernel"] = "k_block (blocked pass)"
     roof["launches"] = nblk
     roof["avg_launch_ms"] = round(avg_ms, 4)
@@ -187,6 +312,15 @@ def main():
                       "readout_abs_diff_vs_fused": abs(gval - val)}
     del state
     torch.cuda.empty_cache()
+
+    if not args.no_variants:
+        out["complex64_32q"] = bench_c64(torch, I, qs)
+        torch.cuda.empty_cache()
+        out["qaoa_batch"] = bench_qaoa(torch, I, qs)
+        torch.cuda.empty_cache()
+    if args.learned:
+        out["learned_planner_33q"] = bench_learned(torch, I, qs)
+        torch.cuda.empty_cache()
 
     if not args.no_cpu:
         log("cpu oracle baseline (bounded sample)")

@@ -78,7 +78,10 @@ typedef struct {
     int low_qubits;       /* L: lowest physical qubits always in the chunk (contiguous 2^L-amplitude runs); 0 = default (4) */
     int enable_swaps;     /* 1: reorder qubits between blocks (folded into block write-back, or standalone swap passes) */
     int enable_fusion;    /* 1: fuse gates inside a block into <= kmax-qubit unitaries / merged diagonals */
-    int planner;          /* 0 = heuristic (gate-count objective, Eq. 7); 1 = learned cost model; 2 = gate-by-gate (no blocking) */
+    int planner;          /* 0 = heuristic (fixed geometry C, r, L); 1 = learned: candidate plans over C, r, L and the
+                             fusion width ranked by the cost model's predicted time, the heuristic kept unless a
+                             candidate is predicted >= 2 % faster; 2 = gate-by-gate (no blocking); 3 = the same
+                             candidates ranked by the number of passes (the paper's objective, Eq. 7) */
     const qs_costmodel *cost_model;  /* required when planner == 1, else NULL */
     qs_dtype dtype;       /* precision the plan will run at (matrices are rounded once, after FP64 composition) */
     int reg_qubits;       /* r: register-resident qubits per thread (4 or 5); 0 = default */
@@ -111,7 +114,7 @@ typedef struct {
     double flops_per_amp; /* sum over ops of algorithmic flops per amplitude (dense k: 8*2^k, diagonal: 6) */
     double hbm_bytes;     /* (blocks + swap_passes) * 2 * 2^n * bytes per amplitude */
     double plan_seconds;  /* host time spent in qs_fuse */
-    int planner;          /* planner that produced the plan: 0 heuristic, 1 learned, 2 gate by gate */
+    int planner;          /* planner that produced the plan: 0 heuristic, 1 learned, 2 gate by gate, 3 pass count */
     int candidates;       /* plans compared (1 unless the learned planner ran) */
     double predicted_ms;  /* learned planner: predicted time of the chosen plan, else -1 */
     double predicted_heuristic_ms; /* learned planner: predicted time of the heuristic plan, else -1 */

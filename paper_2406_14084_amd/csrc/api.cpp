@@ -189,7 +189,7 @@ qs_status qs_fuse(const qs_circuit *circ, int kmax, const qs_plan_opts *opts, qs
     std::string err;
     qs_status rc;
     try {
-        if (opts && opts->planner == 1) rc = qs::build_plan_learned(circ, kmax, opts, &pl->p, &err);
+        if (opts && (opts->planner == 1 || opts->planner == 3)) rc = qs::build_plan_search(circ, kmax, opts, &pl->p, &err);
         else rc = qs::build_plan(circ, kmax, opts, &pl->p, &err);
     } catch (const std::bad_alloc &) {
         rc = QS_ENOMEM;

@@ -10,6 +10,8 @@
 // builds candidate plans over the geometry knobs the heuristic fixes (chunk
 // size C, register bits r, contiguous low bits L, fusion width), and keeps
 // the heuristic plan unless the model predicts a clear gain for another.
+// The same search scored by the paper's own objective -- the fewest passes
+// over the state -- is planner 3, the method without the learned model.
 #include <algorithm>
 #include <array>
 #include <chrono>
@@ -206,9 +208,10 @@ qs_status predict_plans(const qs_costmodel *model, std::vector<Candidate *> &can
 
 }  // namespace
 
-qs_status build_plan_learned(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan *out, std::string *err)
+qs_status build_plan_search(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan *out, std::string *err)
 {
-    if (!o || !o->cost_model) { *err = "qs_fuse: planner 1 (learned) needs a cost model"; return QS_EINVAL; }
+    const bool learned = o && o->planner == 1;
+    if (learned && !o->cost_model) { *err = "qs_fuse: planner 1 (learned) needs a cost model"; return QS_EINVAL; }
     auto t0 = std::chrono::steady_clock::now();
     qs_plan_opts base = *o;
     base.planner = 0;
@@ -269,9 +272,25 @@ qs_status build_plan_learned(const qs_circuit *c, int kmax, const qs_plan_opts *
         seen.push_back(sig);
         keep.push_back(&cd);
     }
+    Candidate *best = &heur;
+    if (!learned) {
+        // the paper's objective (Eq. 7): fewest passes over the state; ties keep the
+        // earlier candidate (the heuristic first), then the fewer flops
+        auto passes = [](const Candidate *cd) { return cd->plan->stats.blocks + cd->plan->stats.swap_passes; };
+        for (Candidate *cd : keep)
+            if (passes(cd) < passes(best) ||
+                (passes(cd) == passes(best) && cd->plan->stats.flops_per_amp < best->plan->stats.flops_per_amp))
+                best = cd;
+        *out = std::move(*best->plan);
+        qs_plan_stats &s = out->stats;
+        s.planner = 3;
+        s.candidates = (int)keep.size();
+        out->plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        s.plan_seconds = out->plan_seconds;
+        return QS_OK;
+    }
     std::string perr;
     rc = predict_plans(o->cost_model, keep, &perr);
-    Candidate *best = &heur;
     if (rc == QS_OK && std::isfinite(heur.pred_ms)) {
         for (Candidate *cd : keep)
             if (std::isfinite(cd->pred_ms) && cd->pred_ms < best->pred_ms) best = cd;

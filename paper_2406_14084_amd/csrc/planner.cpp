@@ -583,6 +583,7 @@ qs_status build_plan(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan 
     if (o) opts = *o;
     else { opts.enable_swaps = 1; opts.enable_fusion = 1; }
     if (opts.dtype != QS_C128 && opts.dtype != QS_C64) { *err = "qs_fuse: bad dtype"; return QS_EINVAL; }
+    if (opts.planner < 0 || opts.planner > 3) { *err = "qs_fuse: planner must be 0..3"; return QS_EINVAL; }
     const int n = c->n;
     p->n = n;
     p->dtype = opts.dtype;

@@ -101,8 +101,9 @@ void encode_plan(Plan *p);
 std::string dump_plan(const Plan &p);
 // Block features for the cost model (48 per step, swap passes included).
 void block_features(const Plan &p, std::vector<float> *out);
-// Learned planner: candidate plans ranked by the cost model (opts->cost_model).
-qs_status build_plan_learned(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan *p, std::string *err);
+// Candidate-plan search: planner 1 ranks by the cost model (opts->cost_model),
+// planner 3 by the number of passes (the paper's objective, Eq. 7).
+qs_status build_plan_search(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan *p, std::string *err);
 
 // ---------------------------------------------------------------------------
 // Program encoding read by the blocked kernel (int32 words per block):

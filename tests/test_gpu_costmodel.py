@@ -176,31 +176,35 @@ def _timed(st, plan, torch):
 
 
 def test_learned_vs_heuristic_33q(torch):
-    """The learned planner's gain on a 33-qubit complex128 circuit (128 GiB)
-    of depth 60 with Haar SU(4) gates on random pairs: time of the learned
-    plan vs the heuristic plan (best of two runs each), amplitudes of the
-    learned plan checked against the heuristic fused path on 4096 sampled
-    indices and on the norm."""
+    """What the trained network gains, on a 33-qubit complex128 circuit
+    (128 GiB) of depth 60 with Haar SU(4) gates on random pairs.  Three plans
+    of the same circuit: the learned planner's, the heuristic's (fixed
+    geometry, also the learned planner's fallback) and the paper's objective
+    over the same candidates (fewest passes, Eq. 7).  The learned plan must
+    not lose to the heuristic and must beat the pass-count choice; all three
+    give the same amplitudes (4096 sampled indices and the norm)."""
     model = trained_model()
     n = 33
     c = I.random_su4(n=n, depth=60, seed=33005)
-    ph = qs.Plan(c, kmax=5)
-    pl = qs.Plan(c, kmax=5, planner=1, cost_model=model)
-    sl = pl.stats()
-    say("33q learned choice C%d r%d L%d planner %d predicted %.0f ms (heuristic predicted %.0f ms)"
-        % (sl["chunk_qubits"], sl["reg_qubits"], sl["low_qubits"], sl["planner"], sl["predicted_ms"],
-           sl["predicted_heuristic_ms"]))
+    plans = {"heuristic": qs.Plan(c, kmax=5), "learned": qs.Plan(c, kmax=5, planner=1, cost_model=model),
+             "passes": qs.Plan(c, kmax=5, planner=3)}
+    for k, p in plans.items():
+        s = p.stats()
+        say("33q %-9s C%d r%d L%d blocks %d swaps %d predicted %.0f ms"
+            % (k, s["chunk_qubits"], s["reg_qubits"], s["low_qubits"], s["blocks"], s["swap_passes"], s["predicted_ms"]))
     st = qs.State(n, "c128")
-    th = _timed(st, ph, torch)
     rng = np.random.default_rng(33)
     idx = torch.from_numpy(rng.integers(0, 1 << n, size=4096)).cuda()
-    ref = st.tensor[idx].cpu().numpy()
-    tl = _timed(st, pl, torch)
-    got = st.tensor[idx].cpu().numpy()
-    norm = st.expect([(0, 0, 1.0)])          # sum of |a|^2 in FP64, no 2^n temporary
-    th = min(th, _timed(st, ph, torch))
-    tl = min(tl, _timed(st, pl, torch))
-    say("33q heuristic %.1f ms  learned %.1f ms  gain %.1f %%" % (th, tl, 100 * (th - tl) / th))
-    assert max_abs_diff(got, ref) <= TOL_C128
-    assert abs(norm - 1.0) <= 1e-10
-    assert tl <= 1.02 * th
+    t, samp = {}, {}
+    for k in ("heuristic", "learned", "passes"):
+        t[k] = _timed(st, plans[k], torch)
+        samp[k] = st.tensor[idx].cpu().numpy()
+        norm = st.expect([(0, 0, 1.0)])          # sum of |a|^2 in FP64, no 2^n temporary
+        say("33q %-9s %.1f ms  norm-1 %.2e" % (k, t[k], norm - 1))
+        assert abs(norm - 1.0) <= 1e-10
+    say("33q gain of the learned plan: %.1f %% vs heuristic, %.1f %% vs fewest passes"
+        % (100 * (t["heuristic"] - t["learned"]) / t["heuristic"], 100 * (t["passes"] - t["learned"]) / t["passes"]))
+    assert max_abs_diff(samp["learned"], samp["heuristic"]) <= TOL_C128
+    assert max_abs_diff(samp["passes"], samp["heuristic"]) <= TOL_C128
+    assert t["learned"] <= 1.02 * t["heuristic"]
+    assert t["learned"] <= 0.95 * t["passes"]

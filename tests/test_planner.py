@@ -197,3 +197,25 @@ def test_learned_planner_needs_model():
     with pytest.raises(qs.QSError) as e:
         qs.Plan(I.random_su4(n=12, depth=4, seed=1), kmax=5, planner=1)
     assert e.value.code == -1
+
+
+def test_pass_count_planner_minimises_passes():
+    """planner=3 (the paper's objective over the candidate geometries) returns
+    a plan with no more passes than any single candidate it searched."""
+    c = I.random_su4(n=24, depth=16, seed=9)
+    p = qs.Plan(c, kmax=5, planner=3)
+    s = p.stats()
+    assert s["planner"] == 3 and s["candidates"] > 1
+    passes = lambda st: st["blocks"] + st["swap_passes"]
+    cands = []
+    for C in (11, 12, 13):
+        for r in (3, 4, 5):
+            for L in (4, 5):
+                for k in (2, 3, 4, 5):
+                    cands.append(passes(qs.Plan(c, kmax=k, chunk_qubits=C, reg_qubits=r, low_qubits=L).stats()))
+    assert passes(s) == min(cands + [passes(qs.Plan(c, kmax=5).stats())])
+
+
+def test_planner_value_checked():
+    with pytest.raises(qs.QSError):
+        qs.Plan(I.random_su4(n=8, depth=2, seed=1), kmax=3, planner=7)
