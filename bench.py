@@ -48,7 +48,7 @@ def sources_sha256():
 
 
 def measured_traffic(n):
-    """HBM bytes per gate-block launch from the counter summary (FETCH_SIZE and
+    """HBM bytes per k_block launch from the counter summary (FETCH_SIZE and
     WRITE_SIZE per dispatch, each scaled by the same counter's reading for a
     copy of known size); None if absent, for another size, or taken on other
     kernel/planner sources."""
@@ -63,7 +63,7 @@ def measured_traffic(n):
     try:
         if kv.get("sources_sha256") != sources_sha256() or int(kv["n"]) != n:
             return None
-        return float(kv["traffic_bytes_per_gate_block"])
+        return float(kv["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
 
