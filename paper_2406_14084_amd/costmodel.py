@@ -60,18 +60,28 @@ def suite(n, rng):
     ]
 
 
-def grid_options(rng, count):
-    """count distinct (C, r, L, k) points of the grid, plus the heuristic default."""
-    pts = [(C, r, L, k) for C in GRID_C for r in GRID_R for L in GRID_L for k in GRID_K]
+def grid(dtype):
+    """(C, r, L, k, matrix cores) points the planner searches for this dtype."""
+    mfs = (True, False) if dtype == "c64" else (True,)
+    return [(C, r, L, k, mf) for C in GRID_C for r in GRID_R for L in GRID_L for k in GRID_K for mf in mfs]
+
+
+def grid_options(rng, count, dtype="c128"):
+    """count distinct grid points, plus the heuristic default."""
+    pts = grid(dtype)
     idx = rng.choice(len(pts), size=min(count, len(pts)), replace=False)
     return [None] + [pts[i] for i in idx]
+
+
+def opt_name(opt):
+    return "heur" if opt is None else "C%dr%dL%dk%d%s" % (opt[:4] + ("" if opt[4] else "v",))
 
 
 def _plan(circ, opt, dtype):
     if opt is None:
         return qs.Plan(circ, kmax=5, dtype=dtype)
-    C, r, L, k = opt
-    return qs.Plan(circ, kmax=k, dtype=dtype, chunk_qubits=C, reg_qubits=r, low_qubits=L)
+    C, r, L, k, mf = opt
+    return qs.Plan(circ, kmax=k, dtype=dtype, chunk_qubits=C, reg_qubits=r, low_qubits=L, mfma=mf)
 
 
 def harvest(sizes=(26, 27, 28, 29, 30, 32), opts_per=(8, 8, 8, 6, 5, 2), dtypes=("c128",), seed=2406,
@@ -87,7 +97,7 @@ def harvest(sizes=(26, 27, 28, 29, 30, 32), opts_per=(8, 8, 8, 6, 5, 2), dtypes=
             for fam, circ in suite(n, rng):
                 if families and fam not in families:
                     continue
-                for opt in grid_options(rng, cnt):
+                for opt in grid_options(rng, cnt, dtype):
                     try:
                         p = _plan(circ, opt, dtype)
                     except qs.QSError:
@@ -99,7 +109,7 @@ def harvest(sizes=(26, 27, 28, 29, 30, 32), opts_per=(8, 8, 8, 6, 5, 2), dtypes=
                     ms = np.minimum(ms, ms2)
                     X.append(f)
                     y.append(target_of(ms, n).astype(np.float32))
-                    tag = "%s/%d/%s/%s" % (fam, n, dtype, "heur" if opt is None else "C%dr%dL%dk%d" % opt)
+                    tag = "%s/%d/%s/%s" % (fam, n, dtype, opt_name(opt))
                     meta += [tag] * len(ms)
                     log("harvest %-28s steps %3d  total %.2f ms" % (tag, len(ms), float(ms.sum())))
                     p.close()
@@ -179,7 +189,7 @@ def rank_check(model, circ, dtype="c128", log=print):
     st = qs.State(circ.n, dtype)
     st.init_zero()
     rows = []
-    for opt in [None] + [(C, r, L, k) for C in GRID_C for r in GRID_R for L in GRID_L for k in GRID_K]:
+    for opt in [None] + grid(dtype):
         try:
             p = _plan(circ, opt, dtype)
         except qs.QSError:
@@ -189,8 +199,7 @@ def rank_check(model, circ, dtype="c128", log=print):
         st.apply_plan_timed(p)
         ms, _ = st.apply_plan_timed(p)
         rows.append((opt, pred, float(ms.sum())))
-        log("rank %-16s predicted %8.2f ms  measured %8.2f ms" % ("heur" if opt is None else "C%dr%dL%dk%d" % opt,
-                                                                   pred, float(ms.sum())))
+        log("rank %-16s predicted %8.2f ms  measured %8.2f ms" % (opt_name(opt), pred, float(ms.sum())))
         p.close()
     torch.cuda.synchronize()
     return rows
@@ -209,6 +218,8 @@ def main(argv=None):
     t.add_argument("--save", action="store_true")
     t.add_argument("--out-dir", default=None, help="write the parameters here instead of the package data folder")
     t.add_argument("--rank-n", type=int, default=0, help="after training, rank all grid plans of a held-out SU(4) circuit")
+    t.add_argument("--rank-c64", type=int, default=0,
+                   help="after training, rank all complex64 grid plans of a held-out U3+CX circuit of this size")
     a = ap.parse_args(argv)
     say = lambda *x: (print(*x), sys.stdout.flush())
     if a.cmd == "harvest":
@@ -226,7 +237,8 @@ def main(argv=None):
         y = np.concatenate([p["y"] for p in parts])
         model, rep = train(X, y, steps=a.steps, log=say)
         rep["data"] = "per-step timings of seeded random circuits at 26-32 qubits (u3cz, u3cx, su4, layered, " \
-                      "dense3, dense2) over the planner's geometry grid; target ln(ps per amplitude)"
+                      "dense3, dense2), complex128 and complex64, over the planner's candidate grid; " \
+                      "target ln(ps per amplitude)"
         say(json.dumps({k: v for k, v in rep.items() if k != "losses"}))
         if a.rank_n:
             rows = rank_check(model, I.random_su4(n=a.rank_n, depth=24, seed=777), log=say)
@@ -235,6 +247,13 @@ def main(argv=None):
             rep["rank_check"] = {"n": a.rank_n, "heuristic_ms": rows[0][2], "best_measured_ms": best_meas[2],
                                  "pick_measured_ms": best_pred[2], "pick": str(best_pred[0])}
             say(json.dumps(rep["rank_check"]))
+        if a.rank_c64:
+            rows = rank_check(model, I.random_u3_2q(n=a.rank_c64, depth=30, seed=778, two="CX"), dtype="c64", log=say)
+            best_meas = min(rows, key=lambda r: r[2])
+            best_pred = min(rows, key=lambda r: r[1])
+            rep["rank_check_c64"] = {"n": a.rank_c64, "heuristic_ms": rows[0][2], "best_measured_ms": best_meas[2],
+                                     "pick_measured_ms": best_pred[2], "pick": str(best_pred[0])}
+            say(json.dumps(rep["rank_check_c64"]))
         if a.save:
             say("saved", save(model, rep, a.out_dir))
 

@@ -353,9 +353,14 @@ __device__ __forceinline__ uint64_t chunk_base(uint64_t c, uint64_t cmask, int n
 // workgroups share a CU, so one's HBM traffic overlaps another's arithmetic.
 // Workgroup size limit: 512 threads when each holds at most 8 amplitudes.
 template <int R> struct MaxThreads { static constexpr int value = (R <= 3) ? 512 : 256; };
+// Two waves per SIMD (two 256-thread workgroups per CU, at most 256 registers
+// per lane) wherever 2^R amplitudes take at most 64 registers; 32 complex128
+// amplitudes (128 registers) get the whole register file instead of spilling.
+template <int R, typename F> struct MinWaves { static constexpr int value = (sizeof(F) * 2 << R) <= 256 ? 2 : 1; };
 
-template <int R, int KMAX, typename F>
-__global__ __launch_bounds__(MaxThreads<R>::value) void k_block(typename AmpOf<F>::type *__restrict__ amps,
+template <int R, int KMAX, typename F, bool MF>
+__global__ __launch_bounds__(MaxThreads<R>::value) __attribute__((amdgpu_waves_per_eu(MinWaves<R, F>::value)))
+void k_block(typename AmpOf<F>::type *__restrict__ amps,
                                               const int *__restrict__ prog, const F *__restrict__ mats, int n)
 {
     using V = typename AmpOf<F>::type;
@@ -472,12 +477,12 @@ __global__ __launch_bounds__(MaxThreads<R>::value) void k_block(typename AmpOf<F
 #pragma unroll
                     for (int m = 0; m < NR; ++m) v[m] = cmul<F, V>(M[2 * m], M[2 * m + 1], v[m]);
                 } else if (kind == OP_MFMA) {
-                    if constexpr (R == 5 && KMAX >= 4 && std::is_same<F, float>::value) {
+                    if constexpr (MF && R == 5 && std::is_same<F, float>::value) {
                         // the wave works in its own 16 KiB of the exchange buffer; other
                         // waves may still be reading this phase's exchange slots there
                         lds_barrier();
                         const float *A = mats + ((int64_t)mlo | ((int64_t)mhi << 32));
-                        mfma_dispatch<KMAX>(variant, v, A, reinterpret_cast<c64 *>(lds_raw) + (tid >> 6) * (64 * 32),
+                        mfma_dispatch<5>(variant, v, A, reinterpret_cast<c64 *>(lds_raw) + (tid >> 6) * (64 * 32),
                                             tid & 63u);
                     }
                 } else if (kind == OP_DIAG_ROW) {   // this lane's row of the op's table (LDS, or device memory)
@@ -503,13 +508,13 @@ __global__ __launch_bounds__(MaxThreads<R>::value) void k_block(typename AmpOf<F
     }
 }
 
-template <int R, int KMAX, typename F>
+template <int R, int KMAX, typename F, bool MF>
 hipError_t launch_RK(qs_state *st, const int *d_prog, const F *d_mats, int C, size_t tab_bytes)
 {
     using V = typename AmpOf<F>::type;
     const size_t lds = ((size_t)1 << C) * sizeof(V) + ((tab_bytes + 15) & ~(size_t)15);
     if (lds > 160u * 1024u) return hipErrorInvalidValue;
-    auto kern = k_block<R, KMAX, F>;
+    auto kern = k_block<R, KMAX, F, MF>;
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
@@ -523,22 +528,31 @@ hipError_t launch_RK(qs_state *st, const int *d_prog, const F *d_mats, int C, si
     return hipGetLastError();
 }
 
+// Kernel variant by the widest vector dense op of the block (2, 3 or R
+// register bits; fewer compiled-in cases keep register pressure and with it
+// occupancy in check), plus the matrix-core variant for complex64 blocks
+// with 4-5-qubit ops (vector ops up to 3 bits beside them).
 template <int R, typename F>
-hipError_t launch_R(qs_state *st, const int *d_prog, const F *d_mats, int C, size_t tab, int kmax)
+hipError_t launch_R(qs_state *st, const int *d_prog, const F *d_mats, int C, size_t tab, int kmax, bool mfma)
 {
-    if (kmax <= 2 || R <= 2) return launch_RK<R, (R < 2 ? R : 2), F>(st, d_prog, d_mats, C, tab);
-    return launch_RK<R, R, F>(st, d_prog, d_mats, C, tab);
+    if constexpr (R == 5 && std::is_same<F, float>::value) {
+        if (mfma) return launch_RK<5, 3, float, true>(st, d_prog, d_mats, C, tab);
+    }
+    if (mfma) return hipErrorInvalidValue;
+    if (kmax <= 2 || R <= 2) return launch_RK<R, (R < 2 ? R : 2), F, false>(st, d_prog, d_mats, C, tab);
+    if (kmax == 3 || R == 3) return launch_RK<R, 3, F, false>(st, d_prog, d_mats, C, tab);
+    return launch_RK<R, R, F, false>(st, d_prog, d_mats, C, tab);
 }
 
 template <typename F>
-hipError_t launch_F(qs_state *st, int r, const int *d_prog, const F *d_mats, int C, size_t tab, int kmax)
+hipError_t launch_F(qs_state *st, int r, const int *d_prog, const F *d_mats, int C, size_t tab, int kmax, bool mfma)
 {
     switch (r) {
-    case 1: return launch_R<1, F>(st, d_prog, d_mats, C, tab, kmax);
-    case 2: return launch_R<2, F>(st, d_prog, d_mats, C, tab, kmax);
-    case 3: return launch_R<3, F>(st, d_prog, d_mats, C, tab, kmax);
-    case 4: return launch_R<4, F>(st, d_prog, d_mats, C, tab, kmax);
-    case 5: return launch_R<5, F>(st, d_prog, d_mats, C, tab, kmax);
+    case 1: return launch_R<1, F>(st, d_prog, d_mats, C, tab, kmax, mfma);
+    case 2: return launch_R<2, F>(st, d_prog, d_mats, C, tab, kmax, mfma);
+    case 3: return launch_R<3, F>(st, d_prog, d_mats, C, tab, kmax, mfma);
+    case 4: return launch_R<4, F>(st, d_prog, d_mats, C, tab, kmax, mfma);
+    case 5: return launch_R<5, F>(st, d_prog, d_mats, C, tab, kmax, mfma);
     default: return hipErrorInvalidValue;
     }
 }
@@ -546,19 +560,21 @@ hipError_t launch_F(qs_state *st, int r, const int *d_prog, const F *d_mats, int
 }  // namespace
 
 hipError_t launch_block_prog(qs_state *st, int r, int C, const int *d_prog, const void *d_mats, size_t tab_bytes,
-                             int kmax_dense)
+                             int kmax_dense, bool mfma)
 {
     if (C < r || st->n < C || (1 << (C - r)) > (r <= 3 ? 512 : 256)) return hipErrorInvalidValue;
+    // matrix-core ops stage each wave's amplitudes in its own slice of the chunk buffer
+    if (mfma && (st->dtype != QS_C64 || r != 5 || C - r < 6)) return hipErrorInvalidValue;
     if (st->dtype == QS_C64)
-        return launch_F<float>(st, r, d_prog, reinterpret_cast<const float *>(d_mats), C, tab_bytes, kmax_dense);
-    return launch_F<double>(st, r, d_prog, reinterpret_cast<const double *>(d_mats), C, tab_bytes, kmax_dense);
+        return launch_F<float>(st, r, d_prog, reinterpret_cast<const float *>(d_mats), C, tab_bytes, kmax_dense, mfma);
+    return launch_F<double>(st, r, d_prog, reinterpret_cast<const double *>(d_mats), C, tab_bytes, kmax_dense, mfma);
 }
 
 hipError_t launch_block(qs_state *st, const Plan &p, int b)
 {
     const int *prog = reinterpret_cast<const int *>(p.d_prog) + p.prog_off[b];
     const size_t tab_bytes = (size_t)p.h_prog[p.prog_off[b] + 5] * 4;
-    return launch_block_prog(st, p.r, p.C, prog, p.d_mats, tab_bytes, p.block_kmax[b]);
+    return launch_block_prog(st, p.r, p.C, prog, p.d_mats, tab_bytes, p.block_kmax[b], p.block_mfma[b] != 0);
 }
 
 }  // namespace qs

@@ -8,7 +8,8 @@
 // planner scores a plan by the sum over its steps of a predicted time,
 //   t(step) = 2^n * exp(model(features(step))) picoseconds,
 // builds candidate plans over the geometry knobs the heuristic fixes (chunk
-// size C, register bits r, contiguous low bits L, fusion width), and keeps
+// size C, register bits r, contiguous low bits L, fusion width, and for
+// complex64 whether 4-5-qubit ops use the matrix cores), and keeps
 // the heuristic plan unless the model predicts a clear gain for another.
 // The same search scored by the paper's own objective -- the fewest passes
 // over the state -- is planner 3, the method without the learned model.
@@ -45,7 +46,7 @@ void block_features(const Plan &p, std::vector<float> *out)
         const int nph = w[0], flags = w[3], tab_words = w[5];
         const bool perm_wb = (flags & 2) != 0;
         int dense[6] = {0}, ndiag_reg = 0, ndiag_row = 0, nsign_reg = 0, nsign_row = 0, nmulti = 0, nmulti_g = 0;
-        int nops = 0, max_ops = 0, swz_phases = 0, diag_bits = 0, full_reg = 0, kdense_max = 0;
+        int nops = 0, max_ops = 0, swz_phases = 0, diag_bits = 0, nmfma = 0, kdense_max = 0;
         double flops = 0, flops_k45 = 0, dense_width = 0, dense_k_sum = 0;
         const int32_t *q = w + PROG_HDR + 2 * C;
         for (int ph = 0; ph < nph; ++ph) {
@@ -64,16 +65,15 @@ void block_features(const Plan &p, std::vector<float> *out)
                     dense_width += 1 << k;
                     dense_k_sum += k;
                     kdense_max = std::max(kdense_max, k);
-                    if (k == r) ++full_reg;
                     break;
                 case OP_MFMA:
                     ++dense[k];
+                    ++nmfma;
                     flops += 8.0 * (1 << k);
                     flops_k45 += 8.0 * (1 << k);
                     dense_width += 1 << k;
                     dense_k_sum += k;
                     kdense_max = std::max(kdense_max, k);
-                    if (k == r) ++full_reg;
                     break;
                 case OP_MULTI1:
                     ++nmulti;
@@ -139,7 +139,7 @@ void block_features(const Plan &p, std::vector<float> *out)
         f[37] = (n - C) / 24.f;
         f[38] = flops > 0 ? (float)(flops_k45 / flops) : 0.f;
         f[39] = (float)(dense_width / 128.0);
-        f[40] = full_reg / 8.f;
+        f[40] = nmfma / 8.f;
         f[41] = swz_phases / 8.f;
         f[42] = kf / 5.f;
         f[43] = diag_bits / 32.f;
@@ -233,19 +233,23 @@ qs_status build_plan_search(const qs_circuit *c, int kmax, const qs_plan_opts *o
     if (base.low_qubits) Ls = {base.low_qubits};
     else Ls = {4, 5};
     for (int k = std::max(1, kmax - 3); k <= kmax; ++k) ks.push_back(k);
+    std::vector<int> mfs{base.no_mfma};
+    if (base.dtype == QS_C64 && !base.no_mfma) mfs.push_back(1);     // matrix cores on and off
     std::vector<Candidate> cands;
     for (int C : Cs)
         for (int r : rs)
             for (int L : Ls)
-                for (int k : ks) {
-                    Candidate cd;
-                    cd.o = base;
-                    cd.o.chunk_qubits = C;
-                    cd.o.reg_qubits = r;
-                    cd.o.low_qubits = L;
-                    cd.kmax = k;
-                    cands.push_back(std::move(cd));
-                }
+                for (int k : ks)
+                    for (int nm : mfs) {
+                        Candidate cd;
+                        cd.o = base;
+                        cd.o.chunk_qubits = C;
+                        cd.o.reg_qubits = r;
+                        cd.o.low_qubits = L;
+                        cd.o.no_mfma = nm;
+                        cd.kmax = k;
+                        cands.push_back(std::move(cd));
+                    }
     // candidate plans are independent: build them on a few host threads
     const int nthr = (int)std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
     std::vector<std::thread> pool;
@@ -264,10 +268,11 @@ qs_status build_plan_search(const qs_circuit *c, int kmax, const qs_plan_opts *o
     for (auto &th : pool) th.join();
     // keep valid, distinct geometries (the planner may widen r or clip C and L)
     std::vector<Candidate *> keep{&heur};
-    std::vector<std::array<int, 4>> seen{{heur.plan->C, heur.plan->r, heur.plan->L, std::min(kmax, heur.plan->r)}};
+    std::vector<std::array<int, 5>> seen{
+        {heur.plan->C, heur.plan->r, heur.plan->L, std::min(kmax, heur.plan->r), heur.plan->mfma ? 1 : 0}};
     for (Candidate &cd : cands) {
         if (cd.rc) continue;
-        std::array<int, 4> sig{cd.plan->C, cd.plan->r, cd.plan->L, std::min(cd.kmax, cd.plan->r)};
+        std::array<int, 5> sig{cd.plan->C, cd.plan->r, cd.plan->L, std::min(cd.kmax, cd.plan->r), cd.plan->mfma ? 1 : 0};
         if (std::find(seen.begin(), seen.end(), sig) != seen.end()) continue;
         seen.push_back(sig);
         keep.push_back(&cd);

@@ -981,16 +981,20 @@ void encode_plan(Plan *p)
     p->h_mats.clear();
     p->prog_off.clear();
     p->block_kmax.clear();
+    p->block_mfma.clear();
     const int C = p->C, r = p->r;
     for (const Block &blk : p->blocks) {
         int64_t start = (int64_t)p->h_prog.size();
         p->prog_off.push_back(start);
         int bk = 0;
+        bool bm = false;
         for (const Phase &P : blk.phases)
             for (const Op &op : P.ops)
-                if (op.kind == OP_DENSE) bk = std::max(bk, op.k);
+                if (op.kind == OP_DENSE && p->mfma && op.k >= 4) bm = true;
+                else if (op.kind == OP_DENSE) bk = std::max(bk, op.k);
                 else if (op.kind == OP_MULTI1) bk = std::max(bk, 1);
         p->block_kmax.push_back(bk);
+        p->block_mfma.push_back(bm ? 1 : 0);
         std::vector<int32_t> w;
         w.push_back((int32_t)blk.phases.size());
         w.push_back(C);

@@ -85,7 +85,8 @@ struct Plan {
     void *d_prog = nullptr;             // int32 program words for all blocks
     void *d_mats = nullptr;             // matrices (FP64 or FP32 by dtype)
     std::vector<int64_t> prog_off;      // per block: offset of its program in d_prog (int32 words)
-    std::vector<int> block_kmax;        // per block: widest dense op (selects the kernel variant)
+    std::vector<int> block_kmax;        // per block: widest vector dense op (selects the kernel variant)
+    std::vector<char> block_mfma;       // per block: has matrix-core ops (complex64 variant with them)
     std::vector<int32_t> h_prog;
     std::vector<double> h_mats;
     std::vector<float> h_mats32;
@@ -176,5 +177,5 @@ hipError_t launch_block(qs_state *st, const Plan &p, int b);
 hipStream_t costmodel_stream(const qs_costmodel *m);
 int costmodel_device(const qs_costmodel *m);
 hipError_t launch_block_prog(qs_state *st, int r, int C, const int *d_prog, const void *d_mats, size_t tab_bytes,
-                             int kmax_dense);
+                             int kmax_dense, bool mfma);
 }
