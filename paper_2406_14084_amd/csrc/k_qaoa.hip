@@ -45,6 +45,7 @@ struct QTask {
 };
 
 constexpr unsigned kSpinLimit = 1u << 24;   // ~1 s of polling before giving up (error flag)
+constexpr int kTaskBatch = 8;               // tasks taken per queue atomic
 
 template <typename F, typename V>
 __device__ __forceinline__ void rx_pair(V &a0, V &a1, F c, F s)
@@ -90,11 +91,17 @@ __global__ __launch_bounds__(THREADS) void k_qaoa(const QInst *__restrict__ inst
     const int tid = threadIdx.x;
 
     for (;;) {
-        if (tid == 0) s_task = (int)atomicAdd(next, 1u);
+        // one atomic per kTaskBatch consecutive tasks: the queue counter is a
+        // single device-wide location shared by all XCDs
+        if (tid == 0) s_task = (int)atomicAdd(next, (unsigned)kTaskBatch);
         __syncthreads();
-        const int t = s_task;
+        const int t0 = s_task;
         __syncthreads();
-        if (t >= ntasks) break;
+        if (t0 >= ntasks) break;
+        const int t1 = min(t0 + kTaskBatch, ntasks);
+        // a task waits only for tasks queued before it: those are either earlier in
+        // this batch (already done here) or were taken by running workgroups
+        for (int t = t0; t < t1; ++t) {
         const QTask tk = tasks[task_begin + t];
         const QInst I = inst[tk.inst];
         for (int i = tid; i < I.nedges; i += THREADS) se[i] = edges[I.edge_off + i];
@@ -224,6 +231,7 @@ __global__ __launch_bounds__(THREADS) void k_qaoa(const QInst *__restrict__ inst
         __syncthreads();
         if (tid == 0) atomicAdd(&done[tk.inst], 1u);
         __syncthreads();
+        }
     }
 }
 

@@ -176,3 +176,26 @@ def test_c64_matrix_core_ops_vs_oracle(torch, n, seed, chunk):
         assert d2 <= rig
         out[mf] = (got, rig)
     assert float(np.linalg.norm(out[True][0] - out[False][0])) <= out[True][1] + out[False][1]
+
+
+def test_c64_max_size_34q_inverse(torch):
+    """Largest supported state (34 qubits, complex64: 128 GiB): a U3 + CX
+    circuit and its inverse, fused and blocked, return |0...0> within the
+    rigorous bound of both plans (indices above 2^32 exercise 64-bit
+    offsets in every kernel on the path)."""
+    n = 34
+    c = I.random_u3_2q(n=n, depth=4, seed=34004, two="CX")
+    say("c64 34q inverse")
+    st = qs.State(n, "c64")
+    st.init_zero()
+    p1 = qs.Plan(c, kmax=5, dtype="c64")
+    p2 = qs.Plan(c.inverse(), kmax=5, dtype="c64")
+    st.apply_plan(p1)
+    st.apply_plan(p2)
+    rig = bound_for(p1)[0] + bound_for(p2)[0]
+    a0 = complex(st.tensor[0].item())
+    norm = st.expect([(0, 0, 1.0)])
+    # ||psi - e0||^2 = norm - 2 Re a0 + 1, accumulated in FP64 on the GPU
+    d2 = math.sqrt(max(0.0, norm - 2 * a0.real + 1.0))
+    say("34q: |a0 - 1| = %.3e  ||psi - e0|| = %.3e  bound %.3e" % (abs(a0 - 1), d2, rig))
+    assert abs(a0 - 1) <= rig and d2 <= rig + 1e-6

@@ -208,3 +208,30 @@ def test_learned_vs_heuristic_33q(torch):
     assert max_abs_diff(samp["passes"], samp["heuristic"]) <= TOL_C128
     assert t["learned"] <= 1.02 * t["heuristic"]
     assert t["learned"] <= 0.95 * t["passes"]
+
+
+def test_learned_vs_heuristic_c64_30q(torch):
+    """complex64 (where the learned search also toggles the matrix cores):
+    30-qubit U3 + CX, depth 60.  The learned plan must not lose to the
+    heuristic (best of two runs each) and both states agree within the sum of
+    their rigorous complex64 bounds."""
+    from tests.test_gpu_c64 import bound_for
+    model = trained_model()
+    n = 30
+    c = I.random_u3_2q(n=n, depth=60, seed=30064, two="CX")
+    ph = qs.Plan(c, kmax=5, dtype="c64")
+    pl = qs.Plan(c, kmax=5, dtype="c64", planner=1, cost_model=model)
+    s = pl.stats()
+    say("c64 30q learned choice C%d r%d L%d planner %d mfma ops %d predicted %.1f ms (heuristic %.1f ms)"
+        % (s["chunk_qubits"], s["reg_qubits"], s["low_qubits"], s["planner"], s["ops_mfma"], s["predicted_ms"],
+           s["predicted_heuristic_ms"]))
+    st = qs.State(n, "c64")
+    th = min(_timed(st, ph, torch) for _ in range(2))
+    a = st.tensor.to(torch.complex128)
+    tl = min(_timed(st, pl, torch) for _ in range(2))
+    d = float(torch.linalg.vector_norm(st.tensor.to(torch.complex128) - a).item())
+    del a
+    say("c64 30q heuristic %.1f ms  learned %.1f ms  gain %.1f %%  ||d||2 %.2e"
+        % (th, tl, 100 * (th - tl) / th, d))
+    assert d <= bound_for(ph)[0] + bound_for(pl)[0]
+    assert tl <= 1.01 * th
