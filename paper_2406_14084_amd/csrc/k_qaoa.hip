@@ -38,6 +38,7 @@ struct QInst {
     long long work_off;  // amplitude offset of the state in the workspace (large only)
     int res;           // output index
     int pad;
+    long long cz_off;  // byte offset of the instance's C(z) values in the cut workspace (large only)
 };
 
 struct QTask {
@@ -45,7 +46,6 @@ struct QTask {
 };
 
 constexpr unsigned kSpinLimit = 1u << 24;   // ~1 s of polling before giving up (error flag)
-constexpr int kTaskBatch = 8;               // tasks taken per queue atomic
 
 template <typename F, typename V>
 __device__ __forceinline__ void rx_pair(V &a0, V &a1, F c, F s)
@@ -58,10 +58,21 @@ __device__ __forceinline__ void rx_pair(V &a0, V &a1, F c, F s)
     a1.y = qfma(c, y.y, -s * x.x);
 }
 
-__device__ __forceinline__ int cut_value(uint64_t z, const int2 *e, int ne)
+// C(z) = number of edges (u, v) with bit u of z != bit v.  The edge list is
+// uniform across the workgroup: read through the constant address space, so
+// the endpoints come in by scalar loads.
+using CInt2 = __attribute__((address_space(4))) int2;
+__device__ __forceinline__ int cut_value(uint64_t z, const CInt2 *e, int ne)
 {
     int c = 0;
-    for (int i = 0; i < ne; ++i) c += (int)(((z >> e[i].x) ^ (z >> e[i].y)) & 1ull);
+    if ((z >> 32) == 0) {
+        const uint32_t z32 = (uint32_t)z;
+#pragma unroll 4
+        for (int i = 0; i < ne; ++i) c += (int)(((z32 >> e[i].x) ^ (z32 >> e[i].y)) & 1u);
+    } else {
+#pragma unroll 4
+        for (int i = 0; i < ne; ++i) c += (int)(((z >> e[i].x) ^ (z >> e[i].y)) & 1ull);
+    }
     return c;
 }
 
@@ -79,32 +90,27 @@ __global__ __launch_bounds__(THREADS) void k_qaoa(const QInst *__restrict__ inst
                                                   int task_begin, int ntasks, const int2 *__restrict__ edges,
                                                   const F *__restrict__ tab, typename AmpOf<F>::type *__restrict__ work,
                                                   unsigned *__restrict__ next, unsigned *__restrict__ done,
-                                                  unsigned *__restrict__ err, double *__restrict__ res)
+                                                  unsigned *__restrict__ err, double *__restrict__ res,
+                                                  unsigned char *__restrict__ czw)
 {
     using V = typename AmpOf<F>::type;
     constexpr int NA = 1 << CB;
     __shared__ V st[NA];
     __shared__ unsigned char cz[NA];
-    __shared__ int2 se[64];
     __shared__ double red[THREADS / 64];
     __shared__ int s_task;
     const int tid = threadIdx.x;
 
     for (;;) {
-        // one atomic per kTaskBatch consecutive tasks: the queue counter is a
-        // single device-wide location shared by all XCDs
-        if (tid == 0) s_task = (int)atomicAdd(next, (unsigned)kTaskBatch);
+        if (tid == 0) s_task = (int)atomicAdd(next, 1u);
         __syncthreads();
-        const int t0 = s_task;
+        const int t = s_task;
         __syncthreads();
-        if (t0 >= ntasks) break;
-        const int t1 = min(t0 + kTaskBatch, ntasks);
-        // a task waits only for tasks queued before it: those are either earlier in
-        // this batch (already done here) or were taken by running workgroups
-        for (int t = t0; t < t1; ++t) {
+        if (t >= ntasks) break;
         const QTask tk = tasks[task_begin + t];
         const QInst I = inst[tk.inst];
-        for (int i = tid; i < I.nedges; i += THREADS) se[i] = edges[I.edge_off + i];
+        const int eoff = __builtin_amdgcn_readfirstlane(I.edge_off);
+        const CInt2 *se = (const CInt2 *)(uintptr_t)(edges + eoff);
         const F *T = tab + I.tab_off;
         const int layer_scalars = 2 * (I.nedges + 1) + 2;
 
@@ -181,7 +187,14 @@ __global__ __launch_bounds__(THREADS) void k_qaoa(const QInst *__restrict__ inst
             } else {
                 st[l] = g[z];
             }
-            if (!second || last_pass) cz[l] = (unsigned char)cut_value(z, se, I.nedges);
+            if (first_pass) {
+                // C(z) once per instance; later passes read it back
+                const unsigned char cv = (unsigned char)cut_value(z, se, I.nedges);
+                cz[l] = cv;
+                czw[I.cz_off + (long long)z] = cv;
+            } else if (!second || last_pass) {
+                cz[l] = czw[I.cz_off + (long long)z];
+            }
         }
         __syncthreads();
         const F *L = T + layer * layer_scalars;
@@ -231,7 +244,6 @@ __global__ __launch_bounds__(THREADS) void k_qaoa(const QInst *__restrict__ inst
         __syncthreads();
         if (tid == 0) atomicAdd(&done[tk.inst], 1u);
         __syncthreads();
-        }
     }
 }
 
@@ -257,6 +269,7 @@ struct qs_batch {
     int device = 0;
     void *d_inst = nullptr, *d_tasks = nullptr, *d_seq_tasks = nullptr, *d_edges = nullptr, *d_tab = nullptr;
     void *d_work = nullptr, *d_ctr = nullptr;
+    void *d_czw = nullptr;   // C(z) bytes of the large instances
     int ntasks = 0;
     std::vector<int> seq_begin, seq_count;   // per instance: its tasks in d_seq_tasks
     int nctr = 0;                            // [0] next, [1] err, [2..2+count) done, then one "next" per sequential launch
@@ -290,12 +303,13 @@ hipError_t launch_qaoa(qs_batch *b, const void *tasks, int begin, int ntasks, un
     const int2 *E = reinterpret_cast<const int2 *>(b->d_edges);
     const F *tab = reinterpret_cast<const F *>(b->d_tab);
     V *work = reinterpret_cast<V *>(b->d_work);
+    unsigned char *czw = reinterpret_cast<unsigned char *>(b->d_czw);
     if (threads == 512)
         hipLaunchKernelGGL((k_qaoa<512, CB, F>), dim3(grid), dim3(512), 0, b->stream, I, T, begin, ntasks, E, tab, work,
-                           next, ctr + 2, ctr + 1, out);
+                           next, ctr + 2, ctr + 1, out, czw);
     else
         hipLaunchKernelGGL((k_qaoa<256, CB, F>), dim3(grid), dim3(256), 0, b->stream, I, T, begin, ntasks, E, tab, work,
-                           next, ctr + 2, ctr + 1, out);
+                           next, ctr + 2, ctr + 1, out, czw);
     return hipGetLastError();
 }
 
@@ -367,6 +381,7 @@ qs_status qs_batch_qaoa_create(int count, const qs_qaoa_instance *inst, qs_dtype
             tab.push_back(std::sin(q.betas[l]));
         }
         d.work_off = d.large ? work : 0;
+        d.cz_off = d.large ? work : 0;        // one byte per amplitude, same layout as the states
         if (d.large) work += 1ll << q.n;
         d.res = i;
         d.pad = 0;
@@ -425,6 +440,7 @@ qs_status qs_batch_qaoa_create(int count, const qs_qaoa_instance *inst, qs_dtype
         alloc(&b->d_tab, tab.size() * sizeof(double), tab.data(), "qs_batch_qaoa_create: tables");
     }
     alloc(&b->d_work, (size_t)work * abytes, nullptr, "qs_batch_qaoa_create: workspace");
+    alloc(&b->d_czw, (size_t)std::max<long long>(work, 1), nullptr, "qs_batch_qaoa_create: cut workspace");
     alloc(&b->d_ctr, (size_t)b->nctr * sizeof(unsigned), nullptr, "qs_batch_qaoa_create: counters");
     if (rc) {
         qs_batch_free(b);
@@ -547,7 +563,7 @@ qs_status qs_batch_free(qs_batch *b)
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
     if (b->gstream) (void)hipStreamDestroy(b->gstream);
-    for (void *p : {b->d_inst, b->d_tasks, b->d_seq_tasks, b->d_edges, b->d_tab, b->d_work, b->d_ctr})
+    for (void *p : {b->d_inst, b->d_tasks, b->d_seq_tasks, b->d_edges, b->d_tab, b->d_work, b->d_ctr, b->d_czw})
         if (p) (void)hipFree(p);
     delete b;
     return QS_OK;
