@@ -245,7 +245,8 @@ typedef struct qs_batch qs_batch;
  * into chunk tasks, two passes per layer.  dtype: QS_C64 (complex64 state,
  * FP64 reductions) or QS_C128.  hip_stream: stream for all work.  Allocates
  * device memory for the tables, queue and workspace, owned by the batch.
- * Launch shape defaults to 256 threads and 2 workgroups per CU until
+ * Launch shape defaults to 256 threads, 2 workgroups per CU and 8 chunks per
+ * task until
  * qs_batch_autotune picks one.  Paper: QAOA is one of the benchmark
  * circuits of Sec. VI-A (Table II); batching is this library's addition. */
 QS_API qs_status qs_batch_qaoa_create(int count, const qs_qaoa_instance *inst, qs_dtype dtype,
@@ -267,9 +268,11 @@ QS_API qs_status qs_batch_free(qs_batch *b);
  * then invalid).  Synchronises the stream. */
 QS_API qs_status qs_batch_error(qs_batch *b, int *err);
 
-/* Choose tile/chunk parameters for the batched kernel by timing candidates
- * on the device for the given batch; writes the chosen config index and
- * leaves it in force for later runs of this batch.  Synchronises. */
+/* Choose the launch shape (threads 256/512 x workgroups per CU, 5 shapes) and
+ * the number of chunks per task of the large instances (2, 8, 32 or 128) by
+ * timing all 20 combinations on the device for this batch; *chosen gets
+ * shape + 5 * grouping, and the choice stays in force for later runs of this
+ * batch (a captured graph is re-captured).  Synchronises. */
 QS_API qs_status qs_batch_autotune(qs_batch *b, int *chosen, double *best_ms);
 
 /* ---- learned cost model (48 -> 128 -> 128 -> 1, FP32) --------------------- */

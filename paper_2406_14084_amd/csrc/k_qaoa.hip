@@ -42,10 +42,16 @@ struct QInst {
 };
 
 struct QTask {
-    int inst, pass, chunk, pad;
+    int inst, pass, chunk, count;   // large instances: chunks [chunk, chunk + count) of one pass
 };
 
 constexpr unsigned kSpinLimit = 1u << 24;   // ~1 s of polling before giving up (error flag)
+// chunks of one pass per batched task (autotuned): each task ends with one
+// agent-scope release, which writes back the XCD's L2, so fewer, larger tasks
+// cost fewer write-backs but leave fewer tasks to spread over the device
+constexpr int kGroups[] = {2, 8, 32, 128};
+constexpr int kNumGroups = 4;
+constexpr int kDefaultGroup = 1;
 
 template <typename F, typename V>
 __device__ __forceinline__ void rx_pair(V &a0, V &a1, F c, F s)
@@ -179,52 +185,58 @@ __global__ __launch_bounds__(THREADS) void k_qaoa(const QInst *__restrict__ inst
         __syncthreads();
         V *g = work + I.work_off;
         const F amp0 = (F)(1.0 / sqrt(ldexp(1.0, I.n)));
-        for (int l = tid; l < NA; l += THREADS) {
-            const uint64_t z = pass_index((uint32_t)l, (uint64_t)tk.chunk, I.n, CB, second);
-            if (first_pass) {
-                st[l].x = amp0;
-                st[l].y = (F)0;
-            } else {
-                st[l] = g[z];
-            }
-            if (first_pass) {
-                // C(z) once per instance; later passes read it back
-                const unsigned char cv = (unsigned char)cut_value(z, se, I.nedges);
-                cz[l] = cv;
-                czw[I.cz_off + (long long)z] = cv;
-            } else if (!second || last_pass) {
-                cz[l] = czw[I.cz_off + (long long)z];
-            }
-        }
-        __syncthreads();
         const F *L = T + layer * layer_scalars;
         const F cb = L[2 * (I.nedges + 1)], sb = L[2 * (I.nedges + 1) + 1];
-        int qlo, qhi;
-        if (!second) {
+        const int qlo = second ? CB - (I.n - CB) : 0, qhi = CB;
+        const int cnt = max(1, tk.count);
+        double acc = 0.0;                  // last pass: this thread's part of <C> over the task's chunks
+        for (int chunk = tk.chunk; chunk < tk.chunk + cnt; ++chunk) {
             for (int l = tid; l < NA; l += THREADS) {
-                const int c = cz[l];
-                st[l] = cmul<F, V>(L[2 * c], L[2 * c + 1], st[l]);
+                const uint64_t z = pass_index((uint32_t)l, (uint64_t)chunk, I.n, CB, second);
+                if (first_pass) {
+                    st[l].x = amp0;
+                    st[l].y = (F)0;
+                } else {
+                    st[l] = g[z];
+                }
+                if (first_pass) {
+                    // C(z) once per instance; later passes read it back
+                    const unsigned char cv = (unsigned char)cut_value(z, se, I.nedges);
+                    cz[l] = cv;
+                    czw[I.cz_off + (long long)z] = cv;
+                } else if (!second || last_pass) {
+                    cz[l] = czw[I.cz_off + (long long)z];
+                }
             }
-            qlo = 0;
-            qhi = CB;
-        } else {
-            qlo = CB - (I.n - CB);
-            qhi = CB;
-        }
-        for (int q = qlo; q < qhi; ++q) {
             __syncthreads();
-            for (int pi = tid; pi < NA / 2; pi += THREADS) {
-                const int l0 = ((pi >> q) << (q + 1)) | (pi & ((1 << q) - 1));
-                rx_pair<F, V>(st[l0], st[l0 | (1 << q)], cb, sb);
+            if (!second) {
+                for (int l = tid; l < NA; l += THREADS) {
+                    const int c = cz[l];
+                    st[l] = cmul<F, V>(L[2 * c], L[2 * c + 1], st[l]);
+                }
             }
+            for (int q = qlo; q < qhi; ++q) {
+                __syncthreads();
+                for (int pi = tid; pi < NA / 2; pi += THREADS) {
+                    const int l0 = ((pi >> q) << (q + 1)) | (pi & ((1 << q) - 1));
+                    rx_pair<F, V>(st[l0], st[l0 | (1 << q)], cb, sb);
+                }
+            }
+            __syncthreads();
+            if (last_pass) {
+                for (int l = tid; l < NA; l += THREADS) {
+                    const double x = (double)st[l].x, y = (double)st[l].y;
+                    acc += (x * x + y * y) * (double)cz[l];
+                }
+            } else {
+                for (int l = tid; l < NA; l += THREADS) {
+                    const uint64_t z = pass_index((uint32_t)l, (uint64_t)chunk, I.n, CB, second);
+                    g[z] = st[l];
+                }
+            }
+            __syncthreads();               // st and cz are refilled by the next chunk
         }
-        __syncthreads();
         if (last_pass) {
-            double acc = 0.0;
-            for (int l = tid; l < NA; l += THREADS) {
-                const double x = (double)st[l].x, y = (double)st[l].y;
-                acc += (x * x + y * y) * (double)cz[l];
-            }
             for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
             if ((tid & 63) == 0) red[tid >> 6] = acc;
             __syncthreads();
@@ -234,15 +246,12 @@ __global__ __launch_bounds__(THREADS) void k_qaoa(const QInst *__restrict__ inst
                 atomicAdd(&res[I.res], s);
             }
         } else {
-            for (int l = tid; l < NA; l += THREADS) {
-                const uint64_t z = pass_index((uint32_t)l, (uint64_t)tk.chunk, I.n, CB, second);
-                g[z] = st[l];
-            }
-            // make the chunk visible to whichever workgroup runs the next pass
+            // make the task's chunks visible to whichever workgroups run the next pass
+            // (one release per task: on this device it writes back the XCD's L2)
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         }
         __syncthreads();
-        if (tid == 0) atomicAdd(&done[tk.inst], 1u);
+        if (tid == 0) atomicAdd(&done[tk.inst], (unsigned)cnt);
         __syncthreads();
     }
 }
@@ -275,6 +284,8 @@ struct qs_batch {
     int nctr = 0;                            // [0] next, [1] err, [2..2+count) done, then one "next" per sequential launch
     int threads = 256;                       // autotuned
     int grid_per_cu = 2;                     // autotuned
+    int group = qs::kDefaultGroup;           // autotuned: index into the chunk groupings
+    int grp_begin[qs::kNumGroups] = {0}, grp_count[qs::kNumGroups] = {0};
     int cus = 256;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -313,7 +324,7 @@ hipError_t launch_qaoa(qs_batch *b, const void *tasks, int begin, int ntasks, un
     return hipGetLastError();
 }
 
-hipError_t run_batch(qs_batch *b, double *out, int threads, int grid_per_cu)
+hipError_t run_batch(qs_batch *b, double *out, int threads, int grid_per_cu, int group)
 {
     using namespace qs;
     unsigned *ctr = reinterpret_cast<unsigned *>(b->d_ctr);
@@ -321,9 +332,10 @@ hipError_t run_batch(qs_batch *b, double *out, int threads, int grid_per_cu)
     hipLaunchKernelGGL(k_qaoa_reset, dim3((nz + 255) / 256), dim3(256), 0, b->stream, ctr, 2 + b->count, out, b->count);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int grid = std::max(1, std::min(b->ntasks, b->cus * grid_per_cu));
-    if (b->dtype == QS_C64) return launch_qaoa<float>(b, b->d_tasks, 0, b->ntasks, ctr, out, threads, grid);
-    return launch_qaoa<double>(b, b->d_tasks, 0, b->ntasks, ctr, out, threads, grid);
+    const int nt = b->grp_count[group], t0 = b->grp_begin[group];
+    const int grid = std::max(1, std::min(nt, b->cus * grid_per_cu));
+    if (b->dtype == QS_C64) return launch_qaoa<float>(b, b->d_tasks, t0, nt, ctr, out, threads, grid);
+    return launch_qaoa<double>(b, b->d_tasks, t0, nt, ctr, out, threads, grid);
 }
 
 }  // namespace
@@ -395,18 +407,24 @@ qs_status qs_batch_qaoa_create(int count, const qs_qaoa_instance *inst, qs_dtype
     std::sort(small.begin(), small.end(), by_n);
     int maxpass = 0;
     for (int i : large) maxpass = std::max(maxpass, 2 * I[i].p);
+    // one queue per chunk grouping, back to back in d_tasks
     std::vector<QTask> tasks;
-    size_t si = 0;
-    for (int s = 0; s < maxpass; ++s) {
-        for (int i : large) {
-            if (s >= 2 * I[i].p) continue;
-            for (int j = 0; j < (1 << (I[i].n - CB)); ++j) tasks.push_back({i, s, j, 0});
+    for (int gi = 0; gi < kNumGroups; ++gi) {
+        b->grp_begin[gi] = (int)tasks.size();
+        size_t si = 0;
+        for (int s = 0; s < maxpass; ++s) {
+            for (int i : large) {
+                if (s >= 2 * I[i].p) continue;
+                const int nch = 1 << (I[i].n - CB), grp = std::min(kGroups[gi], nch);
+                for (int j = 0; j < nch; j += grp) tasks.push_back({i, s, j, grp});
+            }
+            const size_t take = (small.size() * (size_t)(s + 1)) / (size_t)maxpass;
+            for (; si < take; ++si) tasks.push_back({small[si], 0, 0, 0});
         }
-        const size_t take = (small.size() * (size_t)(s + 1)) / (size_t)maxpass;
-        for (; si < take; ++si) tasks.push_back({small[si], 0, 0, 0});
+        for (; si < small.size(); ++si) tasks.push_back({small[si], 0, 0, 0});
+        b->grp_count[gi] = (int)tasks.size() - b->grp_begin[gi];
     }
-    for (; si < small.size(); ++si) tasks.push_back({small[si], 0, 0, 0});
-    b->ntasks = (int)tasks.size();
+    b->ntasks = b->grp_count[kDefaultGroup];
     // per-instance task lists for the sequential reference
     std::vector<QTask> seq;
     b->seq_begin.resize(count);
@@ -415,7 +433,7 @@ qs_status qs_batch_qaoa_create(int count, const qs_qaoa_instance *inst, qs_dtype
         b->seq_begin[i] = (int)seq.size();
         if (I[i].large) {
             for (int s = 0; s < 2 * I[i].p; ++s)
-                for (int j = 0; j < (1 << (I[i].n - CB)); ++j) seq.push_back({i, s, j, 0});
+                for (int j = 0; j < (1 << (I[i].n - CB)); ++j) seq.push_back({i, s, j, 1});
         } else {
             seq.push_back({i, 0, 0, 0});
         }
@@ -456,7 +474,7 @@ qs_status qs_batch_qaoa_run(qs_batch *b, double *out_dev, int use_graph)
     if (!b || !out_dev) { set_error("qs_batch_qaoa_run: null argument"); return QS_EINVAL; }
     (void)hipSetDevice(b->device);
     if (!use_graph) {
-        hipError_t e = run_batch(b, out_dev, b->threads, b->grid_per_cu);
+        hipError_t e = run_batch(b, out_dev, b->threads, b->grid_per_cu, b->group);
         if (e != hipSuccess) return hip_fail(e, "qs_batch_qaoa_run");
         return QS_OK;
     }
@@ -472,7 +490,7 @@ qs_status qs_batch_qaoa_run(qs_batch *b, double *out_dev, int use_graph)
         hipStream_t user = b->stream;
         b->stream = b->gstream;
         hipError_t e = hipStreamBeginCapture(b->gstream, hipStreamCaptureModeThreadLocal);
-        hipError_t e2 = (e == hipSuccess) ? run_batch(b, out_dev, b->threads, b->grid_per_cu) : hipSuccess;
+        hipError_t e2 = (e == hipSuccess) ? run_batch(b, out_dev, b->threads, b->grid_per_cu, b->group) : hipSuccess;
         hipError_t e3 = (e == hipSuccess) ? hipStreamEndCapture(b->gstream, &b->graph) : hipSuccess;
         b->stream = user;
         if (e != hipSuccess) return hip_fail(e, "qs_batch_qaoa_run: begin capture");
@@ -519,8 +537,10 @@ qs_status qs_batch_autotune(qs_batch *b, int *chosen, double *best_ms)
     double *tmp = nullptr;
     hipError_t e = hipMalloc(&tmp, sizeof(double) * b->count);
     if (e != hipSuccess) return hip_fail(e, "qs_batch_autotune: hipMalloc");
-    const int cand[][2] = {{256, 1}, {256, 2}, {256, 4}, {512, 1}, {512, 2}};
-    const int ncand = (int)(sizeof(cand) / sizeof(cand[0]));
+    // launch shapes (threads, workgroups per CU) x chunk groupings
+    const int shapes[][2] = {{256, 1}, {256, 2}, {256, 4}, {512, 1}, {512, 2}};
+    const int nshape = (int)(sizeof(shapes) / sizeof(shapes[0]));
+    const int ncand = nshape * kNumGroups;
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
@@ -530,7 +550,7 @@ qs_status qs_batch_autotune(qs_batch *b, int *chosen, double *best_ms)
         float tbest = 1e30f;
         for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
             e = hipEventRecord(e0, b->stream);
-            if (e == hipSuccess) e = run_batch(b, tmp, cand[c][0], cand[c][1]);
+            if (e == hipSuccess) e = run_batch(b, tmp, shapes[c % nshape][0], shapes[c % nshape][1], c / nshape);
             if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.f;
@@ -543,8 +563,10 @@ qs_status qs_batch_autotune(qs_batch *b, int *chosen, double *best_ms)
     (void)hipEventDestroy(e1);
     (void)hipFree(tmp);
     if (e != hipSuccess) return hip_fail(e, "qs_batch_autotune");
-    b->threads = cand[bi][0];
-    b->grid_per_cu = cand[bi][1];
+    b->threads = shapes[bi % nshape][0];
+    b->grid_per_cu = shapes[bi % nshape][1];
+    b->group = bi / nshape;
+    b->ntasks = b->grp_count[b->group];
     if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
     if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
     if (chosen) *chosen = bi;
