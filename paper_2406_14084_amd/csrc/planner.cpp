@@ -319,6 +319,67 @@ struct PhaseSched {
         return R;
     }
 
+    // Register set for the next phase by a two-phase lookahead: every r-subset
+    // of the allowed bits is scored by the ops it runs now plus the most the
+    // best following phase could run (over the 12 best first choices); a set
+    // that finishes the block scores highest, more so when it keeps clear of
+    // the bits the write-back puts at the low physical positions (which would
+    // need an extra store phase).  Falls back to the greedy choice when the
+    // subsets are too many.  Fewer phases = fewer LDS exchanges.
+    uint32_t choose_R_search(const std::vector<SetOp> &rem, uint32_t allowed, uint32_t all, uint32_t avoid_last) const
+    {
+        const int want = std::min(r, popc(allowed));
+        auto subsets = [&](uint32_t from, int k) {
+            std::vector<int> pos;
+            for (int b = 0; b < C; ++b)
+                if (from >> b & 1) pos.push_back(b);
+            std::vector<uint32_t> out;
+            const int m = (int)pos.size();
+            if (k <= 0 || k > m) return out;
+            for (uint32_t sel = (1u << k) - 1; sel < (1u << m);) {
+                uint32_t R = 0;
+                for (int i = 0; i < m; ++i)
+                    if (sel >> i & 1) R |= 1u << pos[i];
+                out.push_back(R);
+                const uint32_t t = sel | (sel - 1);   // next subset with k bits (Gosper)
+                sel = (t + 1) | (((~t & (t + 1)) - 1) >> (__builtin_ctz(sel) + 1));
+            }
+            return out;
+        };
+        std::vector<uint32_t> s1 = subsets(allowed, want);
+        if (s1.empty() || s1.size() > 1000) return choose_R(rem, allowed);
+        std::vector<std::pair<int, uint32_t>> c1;
+        for (uint32_t R : s1) c1.push_back({count(rem, R, nullptr), R});
+        std::stable_sort(c1.begin(), c1.end(), [](const std::pair<int, uint32_t> &a, const std::pair<int, uint32_t> &b) {
+            return a.first > b.first;
+        });
+        const std::vector<uint32_t> s2 = subsets(all, std::min(r, popc(all)));
+        const long long FINISH = 1ll << 40;
+        long long best_score = -1;
+        uint32_t best = c1.front().second;
+        const size_t K = std::min<size_t>(12, c1.size());
+        for (size_t i = 0; i < c1.size() && (i < K || c1[i].first == (int)rem.size()); ++i) {
+            const uint32_t R = c1[i].second;
+            long long score;
+            if (c1[i].first == (int)rem.size()) {
+                score = FINISH - ((R & avoid_last) ? 1 : 0);
+            } else {
+                std::vector<int> take;
+                count(rem, R, &take);
+                std::vector<char> used(rem.size(), 0);
+                for (int t : take) used[t] = 1;
+                std::vector<SetOp> rest;
+                for (size_t j = 0; j < rem.size(); ++j)
+                    if (!used[j]) rest.push_back(rem[j]);
+                int c2 = 0;
+                for (uint32_t R2 : s2) c2 = std::max(c2, count(rest, R2, nullptr));
+                score = (long long)(c1[i].first + c2) * 1024 + c1[i].first;
+            }
+            if (score > best_score) { best_score = score; best = R; }
+        }
+        return best;
+    }
+
     // fuse the ops of one phase (in order) under register set R.
     //  - a dense op merges into the single op that last touched its bits when
     //    the union stays in registers, within kmax, and costs no more;
@@ -745,7 +806,7 @@ qs_status build_plan(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan 
         bool first = true;
         while (!prem.empty() || first) {
             uint32_t allowed = first ? (all & ~lowmask_in) : all;
-            uint32_t R = PS.choose_R(prem, allowed);
+            uint32_t R = PS.choose_R_search(prem, allowed, all, lowmask_out);
             std::vector<int> takeidx;
             PS.count(prem, R, &takeidx);
             std::vector<SetOp> phase_ops;
