@@ -82,6 +82,53 @@ __device__ __forceinline__ int cut_value(uint64_t z, const CInt2 *e, int ne)
     return c;
 }
 
+// LDS slot of local index l: one pad slot after every 32 amplitudes.
+__device__ __forceinline__ int PAD(int l) { return l + (l >> 5); }
+
+// RX(2b) on G qubits q0..q0+G-1 of the LDS state at once: each thread loads
+// the 2^G amplitudes of one group into registers, applies the G rotations
+// there and writes them back -- one LDS round trip and one barrier per G
+// qubits instead of per qubit.
+template <int G, typename F, typename V, int THREADS>
+__device__ __forceinline__ void rx_group(V *st, int na, int q0, F c, F s, int tid)
+{
+    for (int bi = tid; bi < (na >> G); bi += THREADS) {
+        const int base = ((bi >> q0) << (q0 + G)) | (bi & ((1 << q0) - 1));
+        V a[1 << G];
+#pragma unroll
+        for (int m = 0; m < (1 << G); ++m) a[m] = st[PAD(base | (m << q0))];
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+#pragma unroll
+            for (int m = 0; m < (1 << G); ++m)
+                if (!((m >> j) & 1)) rx_pair<F, V>(a[m], a[m | (1 << j)], c, s);
+#pragma unroll
+        for (int m = 0; m < (1 << G); ++m) st[PAD(base | (m << q0))] = a[m];
+    }
+}
+
+// RX(2b) on qubits qlo..qhi-1 of the LDS state (na amplitudes), up to five
+// at a time (four for complex128 or 512-thread workgroups, to bound registers).
+template <typename F, typename V, int THREADS>
+__device__ __forceinline__ void rx_qubits(V *st, int na, int qlo, int qhi, F c, F s, int tid)
+{
+    constexpr int GMAX = (sizeof(F) == 8 || THREADS == 512) ? 4 : 5;
+    for (int q0 = qlo; q0 < qhi;) {
+        const int g = min(GMAX, qhi - q0);
+        __syncthreads();
+        switch (g) {
+        case 5:
+            if constexpr (GMAX >= 5) rx_group<5, F, V, THREADS>(st, na, q0, c, s, tid);
+            break;
+        case 4: rx_group<4, F, V, THREADS>(st, na, q0, c, s, tid); break;
+        case 3: rx_group<3, F, V, THREADS>(st, na, q0, c, s, tid); break;
+        case 2: rx_group<2, F, V, THREADS>(st, na, q0, c, s, tid); break;
+        default: rx_group<1, F, V, THREADS>(st, na, q0, c, s, tid); break;
+        }
+        q0 += g;
+    }
+}
+
 // Global amplitude index of local index l in chunk j of a pass.
 __device__ __forceinline__ uint64_t pass_index(uint32_t l, uint64_t j, int n, int CB, bool second)
 {
@@ -101,7 +148,9 @@ __global__ __launch_bounds__(THREADS) void k_qaoa(const QInst *__restrict__ inst
 {
     using V = typename AmpOf<F>::type;
     constexpr int NA = 1 << CB;
-    __shared__ V st[NA];
+    // the chunk in LDS, one pad slot per 32 amplitudes (PAD) so that groups of
+    // register-resident qubits read with a lane stride of 33 slots
+    __shared__ V st[NA + NA / 32];
     __shared__ unsigned char cz[NA];
     __shared__ double red[THREADS / 64];
     __shared__ int s_task;
@@ -126,8 +175,8 @@ __global__ __launch_bounds__(THREADS) void k_qaoa(const QInst *__restrict__ inst
             __syncthreads();
             const F amp0 = (F)(1.0 / sqrt((double)na));
             for (int l = tid; l < na; l += THREADS) {
-                st[l].x = amp0;
-                st[l].y = (F)0;
+                st[PAD(l)].x = amp0;
+                st[PAD(l)].y = (F)0;
                 cz[l] = (unsigned char)cut_value((uint64_t)l, se, I.nedges);
             }
             __syncthreads();
@@ -135,21 +184,15 @@ __global__ __launch_bounds__(THREADS) void k_qaoa(const QInst *__restrict__ inst
                 const F *L = T + layer * layer_scalars;
                 for (int l = tid; l < na; l += THREADS) {
                     const int c = cz[l];
-                    st[l] = cmul<F, V>(L[2 * c], L[2 * c + 1], st[l]);
+                    st[PAD(l)] = cmul<F, V>(L[2 * c], L[2 * c + 1], st[PAD(l)]);
                 }
                 const F cb = L[2 * (I.nedges + 1)], sb = L[2 * (I.nedges + 1) + 1];
-                for (int q = 0; q < I.n; ++q) {
-                    __syncthreads();
-                    for (int pi = tid; pi < na / 2; pi += THREADS) {
-                        const int l0 = ((pi >> q) << (q + 1)) | (pi & ((1 << q) - 1));
-                        rx_pair<F, V>(st[l0], st[l0 | (1 << q)], cb, sb);
-                    }
-                }
+                rx_qubits<F, V, THREADS>(st, na, 0, I.n, cb, sb, tid);
                 __syncthreads();
             }
             double acc = 0.0;
             for (int l = tid; l < na; l += THREADS) {
-                const double x = (double)st[l].x, y = (double)st[l].y;
+                const double x = (double)st[PAD(l)].x, y = (double)st[PAD(l)].y;
                 acc += (x * x + y * y) * (double)cz[l];
             }
             for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
@@ -194,10 +237,10 @@ __global__ __launch_bounds__(THREADS) void k_qaoa(const QInst *__restrict__ inst
             for (int l = tid; l < NA; l += THREADS) {
                 const uint64_t z = pass_index((uint32_t)l, (uint64_t)chunk, I.n, CB, second);
                 if (first_pass) {
-                    st[l].x = amp0;
-                    st[l].y = (F)0;
+                    st[PAD(l)].x = amp0;
+                    st[PAD(l)].y = (F)0;
                 } else {
-                    st[l] = g[z];
+                    st[PAD(l)] = g[z];
                 }
                 if (first_pass) {
                     // C(z) once per instance; later passes read it back
@@ -212,26 +255,20 @@ __global__ __launch_bounds__(THREADS) void k_qaoa(const QInst *__restrict__ inst
             if (!second) {
                 for (int l = tid; l < NA; l += THREADS) {
                     const int c = cz[l];
-                    st[l] = cmul<F, V>(L[2 * c], L[2 * c + 1], st[l]);
+                    st[PAD(l)] = cmul<F, V>(L[2 * c], L[2 * c + 1], st[PAD(l)]);
                 }
             }
-            for (int q = qlo; q < qhi; ++q) {
-                __syncthreads();
-                for (int pi = tid; pi < NA / 2; pi += THREADS) {
-                    const int l0 = ((pi >> q) << (q + 1)) | (pi & ((1 << q) - 1));
-                    rx_pair<F, V>(st[l0], st[l0 | (1 << q)], cb, sb);
-                }
-            }
+            rx_qubits<F, V, THREADS>(st, NA, qlo, qhi, cb, sb, tid);
             __syncthreads();
             if (last_pass) {
                 for (int l = tid; l < NA; l += THREADS) {
-                    const double x = (double)st[l].x, y = (double)st[l].y;
+                    const double x = (double)st[PAD(l)].x, y = (double)st[PAD(l)].y;
                     acc += (x * x + y * y) * (double)cz[l];
                 }
             } else {
                 for (int l = tid; l < NA; l += THREADS) {
                     const uint64_t z = pass_index((uint32_t)l, (uint64_t)chunk, I.n, CB, second);
-                    g[z] = st[l];
+                    g[z] = st[PAD(l)];
                 }
             }
             __syncthreads();               // st and cz are refilled by the next chunk
