@@ -154,6 +154,21 @@ def bench_qaoa(torch, I, qs):
             "gate_applications_per_s_batched": round(gates / (batched * 1e-3), 1), "spin_error_flag": err}
 
 
+def bench_qft31(torch, I, qs):
+    """Context only: the 31-qubit QFT (496 gates, complex128, 32 GiB) that the paper times on one
+    A100 (3.6 s there, another machine); here from |0...0> through the fused, blocked path."""
+    c = I.qft(31)
+    p = qs.Plan(c, kmax=5)
+    st = qs.State(31, "c128")
+    ms = _ms(torch, lambda: (st.init_zero(), st.apply_plan(p)))
+    s = p.stats()
+    del st
+    log("qft31: %.1f ms" % ms)
+    return {"workload": "QFT, 31 qubits, complex128 (496 gates: 31 H + 465 controlled phases)", "ms": round(ms, 2),
+            "blocks": s["blocks"], "swap_passes": s["swap_passes"],
+            "paper_a100_seconds": 3.6, "note": "the paper's number is on another machine (one A100): context, not a target"}
+
+
 def bench_learned(torch, I, qs):
     """33-qubit complex128 (128 GiB) depth-60 Haar SU(4) circuit: learned vs heuristic planner."""
     from paper_2406_14084_amd import costmodel
@@ -317,6 +332,8 @@ def main():
         out["complex64_32q"] = bench_c64(torch, I, qs)
         torch.cuda.empty_cache()
         out["qaoa_batch"] = bench_qaoa(torch, I, qs)
+        torch.cuda.empty_cache()
+        out["context_qft31"] = bench_qft31(torch, I, qs)
         torch.cuda.empty_cache()
     if args.learned:
         out["learned_planner_33q"] = bench_learned(torch, I, qs)

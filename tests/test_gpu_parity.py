@@ -72,6 +72,7 @@ def test_layered_16q_vs_oracle(torch):
     dict(n=20, kmax=4, chunk_qubits=10), dict(n=20, kmax=4, chunk_qubits=11, low_qubits=3),
     dict(n=20, kmax=5, reg_qubits=5), dict(n=16, kmax=4, chunk_qubits=8),
     dict(n=21, kmax=3, planner=2), dict(n=20, kmax=3, reg_qubits=3), dict(n=20, kmax=3, chunk_qubits=11, reg_qubits=3),
+    dict(n=20, kmax=4, chunk_qubits=13, reg_qubits=4), dict(n=22, kmax=5, chunk_qubits=13, reg_qubits=4),
 ])
 def test_random_circuits_vs_oracle(torch, cfg):
     cfg = dict(cfg)
