@@ -276,6 +276,12 @@ QS_API qs_status qs_batch_error(qs_batch *b, int *err);
 QS_API qs_status qs_batch_autotune(qs_batch *b, int *chosen, double *best_ms);
 
 /* ---- learned cost model (48 -> 128 -> 128 -> 1, FP32) --------------------- */
+/* The paper's planner minimises the number of passes over the state (Sec. IV,
+ * Eq. 7); the learned planner (qs_fuse with planner = 1) scores candidate
+ * plans by a predicted time per pass instead.  The network itself has no
+ * counterpart in the paper: 48 features per pass (qs_plan_block_features) ->
+ * 128 -> 128 -> 1, ReLU, FP32, trained by MSE on ln(picoseconds per
+ * amplitude) with Adam, all in the library's own kernels. */
 
 #define QS_COST_FEATURES 48
 
@@ -297,7 +303,10 @@ QS_API qs_status qs_costmodel_set_params(qs_costmodel *m, const float *host_in);
 QS_API qs_status qs_costmodel_train_step(qs_costmodel *m, const float *X_dev, const float *y_dev, int B,
                                   float lr, float *loss_host);
 
-/* Forward only: y_dev[b] = model(X_dev[b]) for B rows (device pointers). */
+/* Forward only: y_dev[b] = model(X_dev[b]) for B rows (device pointers), in
+ * chunks of 1024 rows through the model's own activation workspace: calls on
+ * one model (predict, train_step, or qs_fuse with planner 1) must not overlap.
+ * Async on the model's stream. */
 QS_API qs_status qs_costmodel_predict(const qs_costmodel *m, const float *X_dev, float *y_dev, int B);
 
 /* Gradients of the last train step (same layout as the parameters). */
