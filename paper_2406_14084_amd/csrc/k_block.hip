@@ -248,12 +248,12 @@ __device__ __forceinline__ uint32_t pext_u32(uint32_t v, uint32_t mask)
     return r;
 }
 
-// physical offset of a local index
+
+// physical offset of a local index (branch-free, P read by scalar loads)
 __device__ __forceinline__ uint64_t local_to_phys(uint32_t l, const int *__restrict__ P, int C)
 {
     uint64_t o = 0;
-    for (int b = 0; b < C; ++b)
-        if ((l >> b) & 1u) o |= 1ull << P[b];
+    for (int b = 0; b < C; ++b) o |= (uint64_t)((l >> b) & 1u) << P[b];
     return o;
 }
 
@@ -432,12 +432,15 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
             const int *X = T + tb;                 // exchange block of this phase
             if (p > 0) {
                 // ---- exchange from the previous layout to this one through LDS
+                // XOR of the contributions of the thread's set bits, branch-free: a
+                // per-lane condition around the loads makes the compiler issue and wait
+                // for them one at a time
                 uint32_t wt = 0, rt = 0;
-                for (int j = 0; j < tb; ++j)
-                    if ((tid >> j) & 1u) {
-                        wt ^= (uint32_t)X[j];
-                        rt ^= (uint32_t)X[tb + j];
-                    }
+                for (int j = 0; j < tb; ++j) {
+                    const uint32_t sel = 0u - ((tid >> j) & 1u);
+                    wt ^= (uint32_t)X[j] & sel;
+                    rt ^= (uint32_t)X[tb + j] & sel;
+                }
                 const int *wo = X + 2 * tb;
                 const int *ro = wo + NR;
                 lds_barrier();      // previous readers of the buffer are done
