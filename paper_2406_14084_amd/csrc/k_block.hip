@@ -436,10 +436,20 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
                 // per-lane condition around the loads makes the compiler issue and wait
                 // for them one at a time
                 uint32_t wt = 0, rt = 0;
-                for (int j = 0; j < tb; ++j) {
-                    const uint32_t sel = 0u - ((tid >> j) & 1u);
-                    wt ^= (uint32_t)X[j] & sel;
-                    rt ^= (uint32_t)X[tb + j] & sel;
+                const int xt = ph[3];
+                if (xt > 0) {
+                    const int *Xl = ltab + (xt - 1);    // the same words, staged in LDS
+                    for (int j = 0; j < tb; ++j) {
+                        const uint32_t sel = 0u - ((tid >> j) & 1u);
+                        wt ^= (uint32_t)Xl[j] & sel;
+                        rt ^= (uint32_t)Xl[tb + j] & sel;
+                    }
+                } else {
+                    for (int j = 0; j < tb; ++j) {
+                        const uint32_t sel = 0u - ((tid >> j) & 1u);
+                        wt ^= (uint32_t)X[j] & sel;
+                        rt ^= (uint32_t)X[tb + j] & sel;
+                    }
                 }
                 const int *wo = X + 2 * tb;
                 const int *ro = wo + NR;

@@ -1077,6 +1077,7 @@ void encode_plan(Plan *p)
         for (size_t ph = 0; ph < blk.phases.size(); ++ph) {
             const Phase &P = blk.phases[ph];
             uint64_t swz = (ph > 0) ? choose_swizzle(blk.phases[ph - 1].lay, P.lay, C, r) : 0;
+            const size_t hdr = w.size();
             w.push_back((int32_t)P.ops.size());
             w.push_back((int32_t)(uint32_t)(swz & 0xffffffffu));
             w.push_back((int32_t)(uint32_t)(swz >> 32));
@@ -1102,6 +1103,12 @@ void encode_plan(Plan *p)
                 const Layout *pl = has ? &blk.phases[ph - 1].lay : nullptr;
                 for (int j = 0; j < C - r; ++j) w.push_back(has ? (int32_t)(sw(1u << pl->T[j]) * amp_bytes) : 0);
                 for (int j = 0; j < C - r; ++j) w.push_back(has ? (int32_t)(sw(1u << P.lay.T[j]) * amp_bytes) : 0);
+                // a copy of the thread-bit words in the LDS table (header word 3 = its
+                // offset + 1): the kernel reads them per lane without global loads
+                if (has && tab.size() + 2 * (size_t)(C - r) <= tab_cap) {
+                    w[hdr + 3] = (int32_t)tab.size() + 1;
+                    tab.insert(tab.end(), w.end() - 2 * (C - r), w.end());
+                }
                 for (int m = 0; m < NR; ++m) {
                     uint32_t lr = 0;
                     if (has)

@@ -113,7 +113,8 @@ qs_status build_plan_search(const qs_circuit *c, int kmax, const qs_plan_opts *o
 //   [8 .. 8+C)        P_in
 //   [8+C .. 8+2C)     P_out
 //   then per phase:
-//     [0] nops, [1] swz_lo (F nibbles for high bits 0..7), [2] swz_hi (8..15), [3] reserved
+//     [0] nops, [1] swz_lo (F nibbles for high bits 0..7), [2] swz_hi (8..15),
+//     [3] 1 + word offset in the LDS table of a copy of the 2 tb thread-bit words below, or 0
 //     [4 .. 4+r)      R
 //     [4+r .. 4+C)    T
 //     exchange into this phase (zeros for phase 0), LDS byte offsets:

@@ -178,6 +178,11 @@ def replay_block(psi, w, n, R, mats, c64=False):
                 kr ^= np.where((tid >> j) & 1, xr[j], 0)
             assert np.array_equal(kw[:, None] ^ wo[None, :], ws * ab)
             assert np.array_equal(kr[:, None] ^ ro[None, :], rs * ab)
+            xt = int(w[ph + 3])
+            if xt > 0:   # the kernel reads a copy of the thread-bit words from the LDS table
+                a = xt - 1
+                assert a + 2 * tb <= tab_words
+                assert [int(x) for x in w[tab_off + a:tab_off + a + 2 * tb]] == xw + xr
             for s in (ws, rs):
                 assert s.min() >= 0 and s.max() < (1 << C)
                 assert np.unique(s).size == s.size == (1 << C), "exchange is not a bijection"
