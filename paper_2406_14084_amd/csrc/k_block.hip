@@ -76,6 +76,8 @@ __device__ __forceinline__ void apply_dense(V (&v)[1 << R], P M)
     case MM:                                                                              \
         if constexpr ((MM) < (1 << R) && __builtin_popcount(MM) <= KMAX)                  \
             apply_dense<R, ((MM) < (1 << R) ? (MM) : 1), F, V, P>(v, M);                   \
+        else                                                                              \
+            __builtin_unreachable();                                                      \
         break;
 
 template <int R, int KMAX, typename F, typename V, typename P>
@@ -90,7 +92,7 @@ __device__ __forceinline__ void dense_dispatch(int mask, V (&v)[1 << R], P M)
         QS_DENSE_CASE(26) QS_DENSE_CASE(27) QS_DENSE_CASE(28) QS_DENSE_CASE(29) QS_DENSE_CASE(30)
         QS_DENSE_CASE(31)
     default:
-        break;
+        __builtin_unreachable();
     }
 }
 #undef QS_DENSE_CASE
@@ -118,6 +120,7 @@ __device__ __forceinline__ void apply_multi1(V (&v)[1 << R], P M)
 #define QS_MULTI_CASE(MM)                                                                 \
     case MM:                                                                              \
         if constexpr ((MM) < (1 << R)) apply_multi1<R, ((MM) < (1 << R) ? (MM) : 1), F, V, P>(v, M); \
+        else __builtin_unreachable();                                                     \
         break;
 
 template <int R, typename F, typename V, typename P>
@@ -132,7 +135,7 @@ __device__ __forceinline__ void multi1_dispatch(int mask, V (&v)[1 << R], P M)
         QS_MULTI_CASE(26) QS_MULTI_CASE(27) QS_MULTI_CASE(28) QS_MULTI_CASE(29) QS_MULTI_CASE(30)
         QS_MULTI_CASE(31)
     default:
-        break;
+        __builtin_unreachable();
     }
 }
 #undef QS_MULTI_CASE
@@ -215,6 +218,7 @@ __device__ __forceinline__ void apply_mfma(c64 (&v)[32], const float *__restrict
 #define QS_MFMA_CASE(MM)                                                                  \
     case MM:                                                                              \
         if constexpr (__builtin_popcount(MM) <= KMAX) apply_mfma<MM>(v, A, S, lane);      \
+        else __builtin_unreachable();                                                     \
         break;
 
 template <int KMAX>
@@ -224,7 +228,7 @@ __device__ __forceinline__ void mfma_dispatch(int mask, c64 (&v)[32], const floa
     switch (mask) {
         QS_MFMA_CASE(15) QS_MFMA_CASE(23) QS_MFMA_CASE(27) QS_MFMA_CASE(29) QS_MFMA_CASE(30) QS_MFMA_CASE(31)
     default:
-        break;
+        __builtin_unreachable();
     }
 }
 #undef QS_MFMA_CASE
@@ -497,8 +501,10 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
                         const float *A = mats + ((int64_t)mlo | ((int64_t)mhi << 32));
                         mfma_dispatch<5>(variant, v, A, reinterpret_cast<c64 *>(lds_raw) + (tid >> 6) * (64 * 32),
                                             tid & 63u);
+                    } else {
+                        __builtin_unreachable();
                     }
-                } else if (kind == OP_DIAG_ROW) {   // this lane's row of the op's table (LDS, or device memory)
+                } else {   // this lane's row of the op's table (LDS, or device memory)
                     const uint32_t row = pext_u32(tid, (uint32_t)op[1]);
                     const V *E = variant ? reinterpret_cast<const V *>(
                                                mats + ((int64_t)(uint32_t)op[2] | ((int64_t)op[3] << 32))) +

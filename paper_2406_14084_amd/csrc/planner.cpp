@@ -26,6 +26,8 @@
 #include <cstring>
 #include <numeric>
 #include <sstream>
+#include <stdexcept>
+#include <string>
 
 #include "qs_internal.h"
 
@@ -1036,6 +1038,43 @@ uint64_t choose_swizzle(const Layout &from, const Layout &to, int C, int r)
 
 }  // namespace
 
+// Every op word of the encoded program names a code path that the kernel
+// variant chosen for its block has compiled in (the kernel treats any other
+// value as unreachable): kinds 0 and 2..7, dense register masks within the
+// variant's width, matrix-core masks only in matrix-core blocks.
+static void check_program(const Plan &p)
+{
+    const int C = p.C, r = p.r, tb = C - r, NR = 1 << r;
+    for (size_t b = 0; b < p.blocks.size(); ++b) {
+        const int32_t *w = p.h_prog.data() + p.prog_off[b];
+        const int bk = p.block_kmax[b];
+        const bool bm = p.block_mfma[b] != 0;
+        // the dense width compiled into the variant the launcher picks
+        const int kw = bm ? 3 : (bk <= 2 || r <= 2) ? std::min(r, 2) : (bk == 3 || r == 3) ? 3 : r;
+        const int32_t *ph = w + PROG_HDR + 2 * C;
+        for (int q = 0; q < w[0]; ++q) {
+            const int32_t *op = ph + PHASE_HDR + C + 2 * tb + 2 * NR;
+            for (int o = 0; o < ph[0]; ++o, op += OP_WORDS) {
+                const int kind = op[0] & 0xff, var = (op[0] >> 8) & 0xff;
+                bool ok;
+                switch (kind) {
+                case OP_DENSE: ok = var > 0 && var < NR && __builtin_popcount(var) <= kw; break;
+                case OP_MULTI1: ok = var > 0 && var < NR; break;
+                case OP_MFMA:
+                    ok = bm && r == 5 && (var == 15 || var == 23 || var == 27 || var == 29 || var == 30 || var == 31);
+                    break;
+                case OP_DIAG_REG: case OP_DIAG_ROW: case OP_SIGN_REG: case OP_SIGN_ROW: ok = true; break;
+                default: ok = false;
+                }
+                if (!ok)
+                    throw std::logic_error("encoded op (kind " + std::to_string(kind) + ", mask " + std::to_string(var) +
+                                           ") has no kernel path in its block");
+            }
+            ph = op;
+        }
+    }
+}
+
 void encode_plan(Plan *p)
 {
     p->h_prog.clear();
@@ -1265,6 +1304,7 @@ void encode_plan(Plan *p)
     if (p->h_mats.empty()) p->h_mats.push_back(0.0);
     if (p->h_prog.empty()) p->h_prog.push_back(0);
     if (p->dtype == QS_C64 && p->h_mats32.empty()) p->h_mats32.push_back(0.f);
+    check_program(*p);
 }
 
 // ---------------------------------------------------------------------------
