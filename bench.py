@@ -124,8 +124,10 @@ def bench_c64(torch, I, qs):
         p = qs.Plan(c, kmax=5, dtype="c64", mfma=mf)
         s = p.stats()
         ms = _ms(torch, lambda: (st.init_zero(), st.apply_plan(p)))
+        phi = (1 + math.sqrt(5)) / 2
         bound = sum(s["ops_dense"][k] * (math.sqrt(2) * gam(2 ** (k + 1)) + u) * 2 ** (k / 2) for k in range(1, 6)) \
-            + s["ops_diag"] * (math.sqrt(2) * gam(2) + u)
+            + s["ops_diag"] * (math.sqrt(2) * gam(2) + u) \
+            + s["ops_rot"] * (3 * phi ** 2 * (1 + math.sqrt(2)) * u * (1 + 1e-4) + 2e-14)
         res[name] = {"ms": round(ms, 2), "gate_applications_per_s": round(len(c) / (ms * 1e-3), 1),
                      "ops_mfma": s["ops_mfma"], "ops_dense": s["ops_dense"], "blocks": s["blocks"],
                      "swap_passes": s["swap_passes"], "flops_per_amp": s["flops_per_amp"],
@@ -204,6 +206,8 @@ def main():
     ap.add_argument("--n", type=int, default=WORKLOAD["n"])
     ap.add_argument("--chunk", type=int, default=0, help="chunk qubits C (0 = library default)")
     ap.add_argument("--reg-qubits", type=int, default=0, help="register qubits per thread r (0 = default)")
+    ap.add_argument("--no-split", action="store_true",
+                    help="keep single-qubit gates whole (no phase * rotation * phase split)")
     ap.add_argument("--no-variants", action="store_true", help="skip the complex64 and batched-QAOA comparisons")
     ap.add_argument("--learned", action="store_true", help="also compare the learned planner at 33 qubits (128 GiB)")
     args = ap.parse_args()
@@ -222,7 +226,7 @@ def main():
     log("circuit: %d qubits, %d gates" % (n, len(circ)))
 
     t0 = time.perf_counter()
-    plan = qs.Plan(circ, kmax=kmax, chunk_qubits=args.chunk, reg_qubits=args.reg_qubits)
+    plan = qs.Plan(circ, kmax=kmax, chunk_qubits=args.chunk, reg_qubits=args.reg_qubits, split=not args.no_split)
     plan_s = time.perf_counter() - t0
     st_plan = plan.stats()
     log("plan: %d blocks + %d swap passes, %.3f s" % (st_plan["blocks"], st_plan["swap_passes"], plan_s))
@@ -274,7 +278,7 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": round(ach_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach_gbs / HBM_PEAK_GBS, 4)}
-    tr = measured_traffic(n) if (args.chunk == 0 and args.reg_qubits == 0) else None
+    tr = measured_traffic(n) if (args.chunk == 0 and args.reg_qubits == 0 and not args.no_split) else None
     roof["traffic"] = tr
     if tr is not None:
         roof["traffic_over_algorithmic"] = round(tr / pass_bytes, 4)

@@ -86,6 +86,9 @@ typedef struct {
     qs_dtype dtype;       /* precision the plan will run at (matrices are rounded once, after FP64 composition) */
     int reg_qubits;       /* r: register-resident qubits per thread (4 or 5); 0 = default */
     int no_mfma;          /* complex64: 1 keeps dense ops of 4-5 qubits on vector FMA instead of matrix cores */
+    int no_split;         /* 1 keeps single-qubit gates whole; 0 (default, with fusion on) applies each unitary
+                             single-qubit gate as diag * real rotation * diag: the rotation runs as three in-place
+                             shears (3 FMAs per amplitude instead of 8), the diagonals merge with their neighbours */
 } qs_plan_opts;
 
 /* One Pauli string times a real coefficient.  Per qubit q the letter is
@@ -111,7 +114,7 @@ typedef struct {
     int chunk_qubits;
     int low_qubits;
     int reg_qubits;
-    double flops_per_amp; /* sum over ops of algorithmic flops per amplitude (dense k: 8*2^k, diagonal: 6) */
+    double flops_per_amp; /* sum over ops of algorithmic flops per amplitude (dense k: 8*2^k, diagonal: 6, rotation: 6) */
     double hbm_bytes;     /* (blocks + swap_passes) * 2 * 2^n * bytes per amplitude */
     double plan_seconds;  /* host time spent in qs_fuse */
     int planner;          /* planner that produced the plan: 0 heuristic, 1 learned, 2 gate by gate, 3 pass count */
@@ -119,6 +122,7 @@ typedef struct {
     double predicted_ms;  /* learned planner: predicted time of the chosen plan, else -1 */
     double predicted_heuristic_ms; /* learned planner: predicted time of the heuristic plan, else -1 */
     int ops_mfma;         /* dense ops (counted in ops_dense too) that run on matrix cores */
+    int ops_rot;          /* single-qubit real rotations applied as shears (one per bit of each rotation op) */
 } qs_plan_stats;
 
 /* ---- state handles ------------------------------------------------------ */

@@ -140,6 +140,61 @@ __device__ __forceinline__ void multi1_dispatch(int mask, V (&v)[1 << R], P M)
 }
 #undef QS_MULTI_CASE
 
+// Real plane rotation on each register bit of MASK (ascending), as three shears
+// per amplitude pair (x0, x1) = (bit clear, bit set): x0 += a x1, x1 += b x0,
+// x0 += a x1, on the real and imaginary parts alike -- in place, one FMA each.
+// Coefficients (a, b) of the bits back to back.
+__device__ __forceinline__ double fma_f(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_f(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+template <int R, int MASK, int J, typename F, typename V, typename P>
+__device__ __forceinline__ void apply_rot_from(V (&v)[1 << R], P M)
+{
+    if constexpr (J < R) {
+        if constexpr ((MASK >> J) & 1) {
+            const F a = M[0], b = M[1];
+#pragma unroll
+            for (int base = 0; base < (1 << R); ++base) {
+                if (base & (1 << J)) continue;
+                V &x0 = v[base];
+                V &x1 = v[base | (1 << J)];
+                x0.x = fma_f(a, x1.x, x0.x);
+                x0.y = fma_f(a, x1.y, x0.y);
+                x1.x = fma_f(b, x0.x, x1.x);
+                x1.y = fma_f(b, x0.y, x1.y);
+                x0.x = fma_f(a, x1.x, x0.x);
+                x0.y = fma_f(a, x1.y, x0.y);
+            }
+            apply_rot_from<R, MASK, J + 1, F, V, P>(v, M + 2);
+        } else {
+            apply_rot_from<R, MASK, J + 1, F, V, P>(v, M);
+        }
+    }
+}
+
+#define QS_ROT_CASE(MM)                                                                   \
+    case MM:                                                                              \
+        if constexpr ((MM) < (1 << R)) apply_rot_from<R, ((MM) < (1 << R) ? (MM) : 1), 0, F, V, P>(v, M); \
+        else __builtin_unreachable();                                                     \
+        break;
+
+template <int R, typename F, typename V, typename P>
+__device__ __forceinline__ void rot_dispatch(int mask, V (&v)[1 << R], P M)
+{
+    switch (mask) {
+        QS_ROT_CASE(1) QS_ROT_CASE(2) QS_ROT_CASE(3) QS_ROT_CASE(4) QS_ROT_CASE(5)
+        QS_ROT_CASE(6) QS_ROT_CASE(7) QS_ROT_CASE(8) QS_ROT_CASE(9) QS_ROT_CASE(10)
+        QS_ROT_CASE(11) QS_ROT_CASE(12) QS_ROT_CASE(13) QS_ROT_CASE(14) QS_ROT_CASE(15)
+        QS_ROT_CASE(16) QS_ROT_CASE(17) QS_ROT_CASE(18) QS_ROT_CASE(19) QS_ROT_CASE(20)
+        QS_ROT_CASE(21) QS_ROT_CASE(22) QS_ROT_CASE(23) QS_ROT_CASE(24) QS_ROT_CASE(25)
+        QS_ROT_CASE(26) QS_ROT_CASE(27) QS_ROT_CASE(28) QS_ROT_CASE(29) QS_ROT_CASE(30)
+        QS_ROT_CASE(31)
+    default:
+        __builtin_unreachable();
+    }
+}
+#undef QS_ROT_CASE
+
 // bits of v selected by MASK, packed to the low end (compile time)
 template <int MASK>
 __device__ __forceinline__ constexpr int pext_c(int v)
@@ -479,6 +534,8 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
                 const CF *M = (const CF *)(uintptr_t)(mats + ((int64_t)mlo | ((int64_t)mhi << 32)));
                 if (kind == OP_MULTI1) {
                     multi1_dispatch<R, F, V, const CF *>(variant, v, M);
+                } else if (kind == OP_ROT) {
+                    rot_dispatch<R, F, V, const CF *>(variant, v, M);
                 } else if (kind == OP_DENSE) {
                     dense_dispatch<R, KMAX, F, V, const CF *>(variant, v, M);
                 } else if (kind == OP_SIGN_ROW) {

@@ -81,6 +81,11 @@ void block_features(const Plan &p, std::vector<float> *out)
                     flops += 16.0 * popc((uint32_t)mask);
                     kdense_max = std::max(kdense_max, 1);
                     break;
+                case OP_ROT:     // grouped like the single-qubit ops, at its own arithmetic
+                    ++nmulti;
+                    nmulti_g += popc((uint32_t)mask);
+                    flops += 6.0 * popc((uint32_t)mask);
+                    break;
                 case OP_DIAG_REG: ++ndiag_reg; flops += 6; diag_bits += k; break;
                 case OP_DIAG_ROW: ++ndiag_row; flops += 6; diag_bits += k; break;
                 case OP_SIGN_REG: ++nsign_reg; diag_bits += k; break;

@@ -21,6 +21,7 @@
 //   local indices differ in r chosen chunk bits, and every dense op of the
 //   phase acts on those bits only, so it runs from registers.
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -148,8 +149,11 @@ std::vector<char> choose_chunk(Blocker &B, const std::vector<int> &rem, const st
 // ---------------------------------------------------------------------------
 struct SetOp {
     bool diag = false;
+    bool rot = false;            // real plane rotations (one per bit of mask); m = their dense matrix when one bit
+    bool pin = false;            // diagonal split off a single-qubit gate: runs only while its bits are in registers
     uint32_t mask = 0;           // local chunk bits
     std::vector<cplx> m;         // dense: d*d; diag: d
+    std::vector<std::array<double, 3>> rots;   // rot: (local bit, a, b) of the shears of each bit
     std::vector<int> gate_ids;
 };
 
@@ -215,6 +219,7 @@ SetOp compose(const SetOp &e, const SetOp &o)
     r.gate_ids.insert(r.gate_ids.end(), o.gate_ids.begin(), o.gate_ids.end());
     if (e.diag && o.diag) {
         r.diag = true;
+        r.pin = e.pin || o.pin;
         int d = 1 << popc(r.mask);
         r.m.resize(d);
         for (int u = 0; u < d; ++u) {
@@ -237,6 +242,41 @@ double op_cost(bool diag, int k, bool mfma = false)
     if (diag) return 5.0;
     if (mfma && k >= 4) return 2.0 * (double)(1 << k) + 8.0;
     return 4.0 * (double)(1 << k);
+}
+// a real rotation by three shears: three FMAs per amplitude (real and imaginary parts)
+constexpr double kRotCost = 3.0;
+
+// Single-qubit gate as diag(p) * Rot(theta) * diag(q), Rot = [[c, -s], [s, c]] with
+// c = cos theta, s = sin theta, theta in [0, pi/2] (the phases absorb every sign).
+// For a unitary U: c = |u00|, s = |u10|, q = (1, q1), p0 q0 = u00 / c, p1 q0 = u10 / s,
+// -p0 s q1 = u01.  The rotation runs as three shears (a = -tan(theta/2), b = sin theta):
+//     [[1, a], [0, 1]] [[1, 0], [b, 1]] [[1, a], [0, 1]] = Rot(theta)
+// (1 + ab = cos theta, a (2 + ab) = -sin theta), each shear one FMA per real component,
+// in place, coefficients of magnitude <= 1.  Accepted only when the product of the
+// factors reproduces U to 1e-14 (a non-unitary matrix stays a dense gate); diagonal
+// gates (s = 0) never come here.
+bool split_rotation(const std::vector<cplx> &u, cplx *pre, cplx *post, double *a, double *b, std::vector<cplx> *rot)
+{
+    const cplx u00 = u[0], u01 = u[1], u10 = u[2], u11 = u[3];
+    const double theta = std::atan2(std::abs(u10), std::abs(u00));
+    const double c = std::cos(theta), s = std::sin(theta);
+    if (!(s > 1e-6)) return false;
+    const cplx p0 = std::abs(u00) > 0 ? u00 / std::abs(u00) : cplx(1, 0);
+    const cplx p1 = u10 / std::abs(u10);
+    const cplx q1 = -u01 * std::conj(p0) / s;
+    if (std::abs(std::abs(q1) - 1.0) > 1e-14) return false;
+    const cplx rec[4] = {p0 * c, -p0 * s * q1, p1 * s, p1 * c * q1};
+    for (int i = 0; i < 4; ++i)
+        if (std::abs(rec[i] - u[i]) > 1e-14) return false;
+    (void)u11;
+    pre[0] = cplx(1, 0);
+    pre[1] = q1;
+    post[0] = p0;
+    post[1] = p1;
+    *a = -std::tan(0.5 * theta);
+    *b = s;
+    *rot = {cplx(c, 0), cplx(-s, 0), cplx(s, 0), cplx(c, 0)};
+    return true;
 }
 
 // Convert a circuit gate to a set op over local bits (loc[j] = local bit of t[j]).
@@ -275,22 +315,26 @@ struct PhaseSched {
     bool fuse;
     bool mfma;      // dense ops of k >= 4 run on matrix cores
 
-    // count executable ops with register set Rmask; dense ops need mask subset.
+    // count executable ops with register set Rmask; dense ops (and diagonals split
+    // off single-qubit gates) need their bits in registers.  An op that cannot run
+    // blocks its bits for later ops, except that diagonals commute with each other:
+    // a diagonal left behind blocks only non-diagonal ops.
     int count(const std::vector<SetOp> &rem, uint32_t Rmask, std::vector<int> *take) const
     {
-        uint32_t blocked = 0;
+        uint32_t blocked = 0, blocked_diag = 0;
         int cnt = 0;
         for (size_t i = 0; i < rem.size(); ++i) {
             const SetOp &o = rem[i];
-            bool ok = !(o.mask & blocked) && (o.diag || (o.mask & ~Rmask) == 0);
+            const bool in_regs = (o.mask & ~Rmask) == 0;
+            const bool ok = o.diag ? !(o.mask & blocked) && (!o.pin || in_regs)
+                                   : !(o.mask & (blocked | blocked_diag)) && in_regs;
             if (ok) {
                 ++cnt;
                 if (take) take->push_back((int)i);
+            } else if (o.diag) {
+                blocked_diag |= o.mask;
             } else {
                 blocked |= o.mask;
-                if ((blocked & Rmask) == Rmask && Rmask) {
-                    // every register bit blocked: only diagonals on free bits can still run
-                }
             }
         }
         return cnt;
@@ -389,6 +433,94 @@ struct PhaseSched {
     //    they are a subset, otherwise into the latest diagonal op F such that
     //    every op after F that shares its bits is itself diagonal (diagonals
     //    commute), as long as the merged diagonal has at most kMaxDiagBits bits.
+    // Order of the fused ops of one phase, by list scheduling over their
+    // dependences (ops sharing a bit depend on each other unless both are
+    // diagonal): whenever diagonals are ready they go out first, merged into as
+    // few ops as kMaxDiagBits and the rules below allow (a +-1 diagonal stays a
+    // free sign flip unless it joins a register-bit table); then all ready
+    // rotations as one op; otherwise the earliest ready op.  A layer of split
+    // single-qubit gates thus becomes one diagonal, one rotation op over all its
+    // register bits, and one diagonal shared with the next layer.
+    std::vector<SetOp> reschedule(const std::vector<SetOp> &ops, uint32_t R) const
+    {
+        const size_t n = ops.size();
+        std::vector<std::vector<int>> succ(n);
+        std::vector<int> pending(n, 0);     // undone predecessors
+        for (size_t j = 0; j < n; ++j)
+            for (size_t i = 0; i < j; ++i)
+                if ((ops[i].mask & ops[j].mask) && !(ops[i].diag && ops[j].diag)) {
+                    succ[i].push_back((int)j);
+                    ++pending[j];
+                }
+        auto is_sign = [](const SetOp &x) {
+            for (const cplx &z : x.m)
+                if (!(z.imag() == 0.0 && (z.real() == 1.0 || z.real() == -1.0))) return false;
+            return true;
+        };
+        std::vector<char> done(n, 0);
+        std::vector<SetOp> out;
+        size_t left = n;
+        std::vector<int> finished;          // ops emitted in this round
+        while (left) {
+            for (int i : finished)
+                for (int j : succ[i]) --pending[j];
+            finished.clear();
+            std::vector<int> ready;
+            for (size_t j = 0; j < n; ++j)
+                if (!done[j] && pending[j] == 0) ready.push_back((int)j);
+            std::vector<int> rd, rr;
+            for (int j : ready) {
+                if (ops[j].diag) rd.push_back(j);
+                else if (ops[j].rot) rr.push_back(j);
+            }
+            if (!rd.empty()) {
+                std::vector<SetOp> groups;
+                for (int j : rd) {
+                    const SetOp &o = ops[j];
+                    bool placed = false;
+                    for (SetOp &g : groups) {
+                        const uint32_t U = g.mask | o.mask;
+                        if (popc(U) > kMaxDiagBits) continue;
+                        const bool same = is_sign(g) == is_sign(o) && diag_merge_ok(g, o, R);
+                        if (same || (U & ~R) == 0) { g = compose(g, o); placed = true; break; }
+                    }
+                    if (!placed) groups.push_back(o);
+                    done[j] = 1;
+                    finished.push_back(j);
+                    --left;
+                }
+                for (SetOp &g : groups) out.push_back(std::move(g));
+            } else if (!rr.empty()) {
+                SetOp g;
+                g.rot = true;
+                for (int j : rr) {
+                    g.mask |= ops[j].mask;
+                    g.rots.insert(g.rots.end(), ops[j].rots.begin(), ops[j].rots.end());
+                    g.gate_ids.insert(g.gate_ids.end(), ops[j].gate_ids.begin(), ops[j].gate_ids.end());
+                    done[j] = 1;
+                    finished.push_back(j);
+                    --left;
+                }
+                if (rr.size() == 1) g.m = ops[rr[0]].m;
+                out.push_back(std::move(g));
+            } else {
+                out.push_back(ops[ready.front()]);
+                done[ready.front()] = 1;
+                finished.push_back(ready.front());
+                --left;
+            }
+        }
+        return out;
+    }
+
+    // Two diagonals merge freely, except that one split off a single-qubit gate
+    // only merges into a diagonal on register bits (the merged op stays a
+    // uniform per-register table instead of a per-lane one).
+    static bool diag_merge_ok(const SetOp &f, const SetOp &o, uint32_t R)
+    {
+        return !(f.pin || o.pin) || ((f.mask | o.mask) & ~R) == 0;
+    }
+
     std::vector<SetOp> fuse_phase(const std::vector<SetOp> &ops, uint32_t R) const
     {
         std::vector<SetOp> out;
@@ -409,20 +541,25 @@ struct PhaseSched {
                 SetOp &f = out[F];
                 uint32_t U = f.mask | o.mask;
                 int kU = popc(U);
-                double before = op_cost(f.diag, popc(f.mask), mfma) + op_cost(o.diag, popc(o.mask), mfma);
+                auto cost = [&](const SetOp &x) { return x.rot ? kRotCost : op_cost(x.diag, popc(x.mask), mfma); };
+                double before = cost(f) + cost(o);
                 bool ok;
-                if (f.diag && o.diag) ok = kU <= kMaxDiagBits;
-                else if (!f.diag && o.diag) ok = (o.mask & ~f.mask) == 0;
+                // split-off phases merge later, in reschedule, once a whole layer is ready
+                if (f.diag && o.diag) ok = kU <= kMaxDiagBits && !f.pin && !o.pin;
+                else if (!f.diag && o.diag) ok = !f.rot && (o.mask & ~f.mask) == 0;
+                else if (f.diag && o.rot) ok = false;        // keep the split: the phase stays a cheap diagonal
                 else ok = (U & ~R) == 0 && kU <= kmax && op_cost(false, kU, mfma) <= before;
                 if (ok) {
                     f = compose(f, o);
                     merged_into = F;
                 }
             }
-            if (fuse && merged_into < 0 && o.diag) {
-                // latest diagonal F with only diagonals after it on o's bits
+            if (fuse && merged_into < 0 && o.diag && !o.pin) {
+                // the latest diagonal F with only diagonals after it on o's bits
+                // (diagonals commute; split-off phases are passed over)
                 for (int i = (int)out.size() - 1; i >= 0; --i) {
                     if (out[i].diag) {
+                        if (out[i].pin) continue;
                         if (popc(out[i].mask | o.mask) <= kMaxDiagBits) {
                             out[i] = compose(out[i], o);
                             merged_into = i;
@@ -449,6 +586,22 @@ Op to_kernel_op(const SetOp &s, const Layout &lay, int r)
     op.gate_ids = s.gate_ids;
     op.k = popc(s.mask);
     op.m = s.m;
+    if (s.rot) {
+        // coefficients (a, b) per register bit, ascending register index
+        op.kind = OP_ROT;
+        op.m.clear();
+        int mask = 0;
+        for (int j = 0; j < r; ++j)
+            for (const auto &t : s.rots)
+                if ((int)t[0] == lay.R[j]) {
+                    mask |= 1 << j;
+                    op.m.push_back(cplx(t[1], t[2]));
+                }
+        op.regmask = mask;
+        if (popc((uint32_t)mask) != (int)s.rots.size())
+            throw std::logic_error("rotation op on a bit outside the phase's registers");
+        return op;
+    }
     if (s.diag) {
         op.kind = OP_DIAG;
         int i = 0;
@@ -708,6 +861,8 @@ qs_status build_plan(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan 
     // matrix-core ops: complex64, five register bits, whole wavefronts of threads
     p->mfma = opts.dtype == QS_C64 && !opts.no_mfma && r == 5 && C - r >= 6;
     PhaseSched PS{C, r, L, kf, opts.enable_fusion != 0, p->mfma};
+    // single-qubit gates as phase * rotation * phase (needs the fusion pass to pay off)
+    const bool split = opts.enable_fusion && !opts.no_split && !gbg;
 
     auto emit_block = [&](const std::vector<char> &inS, const std::vector<int> &take, bool last) {
         Block blk;
@@ -724,8 +879,28 @@ qs_status build_plan(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan 
             const GateIn &G = gates[gi];
             int loc[5];
             for (int j = 0; j < G.k; ++j) loc[j] = loc_of_phys[l2p[G.t[j]]];
-            ops.push_back(gate_to_setop(G, loc, gi));
             blk.gate_ids.push_back(gi);
+            cplx pre[2], post[2];
+            double ra, rb;
+            std::vector<cplx> rm;
+            if (split && G.k == 1 && !G.diag && split_rotation(G.m, pre, post, &ra, &rb, &rm)) {
+                // phase, rotation, phase: the phases merge with neighbouring diagonals
+                SetOp d0, rt, d1;
+                d0.diag = d1.diag = true;
+                d0.pin = d1.pin = true;
+                d0.mask = rt.mask = d1.mask = 1u << loc[0];
+                d0.m = {pre[0], pre[1]};
+                d1.m = {post[0], post[1]};
+                rt.rot = true;
+                rt.m = rm;
+                rt.rots.push_back({(double)loc[0], ra, rb});
+                rt.gate_ids.push_back(gi);
+                ops.push_back(std::move(d0));
+                ops.push_back(std::move(rt));
+                ops.push_back(std::move(d1));
+                continue;
+            }
+            ops.push_back(gate_to_setop(G, loc, gi));
         }
         // ---- output placement (folded swap)
         std::vector<int> newpos(C);   // local bit b (logical p2l[P_in[b]]) -> physical
@@ -821,7 +996,9 @@ qs_status build_plan(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan 
             Phase ph;
             ph.lay = make_layout(R, C, r, nullptr);
             std::vector<Op> kops;
-            for (const SetOp &s : PS.fuse_phase(phase_ops, R)) kops.push_back(to_kernel_op(s, ph.lay, r));
+            std::vector<SetOp> fused = PS.fuse_phase(phase_ops, R);
+            if (opts.enable_fusion) fused = PS.reschedule(fused, R);
+            for (const SetOp &s : fused) kops.push_back(to_kernel_op(s, ph.lay, r));
             ph.ops = opts.enable_fusion ? group_single_qubit(kops, ph.lay, r) : kops;
             blk.phases.push_back(ph);
             first = false;
@@ -956,6 +1133,7 @@ qs_status build_plan(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan 
                 ++s.ops;
                 if (op.kind == OP_DIAG) { ++s.ops_diag; s.flops_per_amp += 6.0; }
                 else if (op.kind == OP_MULTI1) { s.ops_dense[1] += op.k; s.flops_per_amp += 16.0 * op.k; }
+                else if (op.kind == OP_ROT) { s.ops_rot += op.k; s.flops_per_amp += 6.0 * op.k; }
                 else {
                     ++s.ops_dense[op.k];
                     s.flops_per_amp += 8.0 * (double)(1 << op.k);
@@ -1040,7 +1218,7 @@ uint64_t choose_swizzle(const Layout &from, const Layout &to, int C, int r)
 
 // Every op word of the encoded program names a code path that the kernel
 // variant chosen for its block has compiled in (the kernel treats any other
-// value as unreachable): kinds 0 and 2..7, dense register masks within the
+// value as unreachable): kinds 0 and 2..8, dense register masks within the
 // variant's width, matrix-core masks only in matrix-core blocks.
 static void check_program(const Plan &p)
 {
@@ -1059,7 +1237,7 @@ static void check_program(const Plan &p)
                 bool ok;
                 switch (kind) {
                 case OP_DENSE: ok = var > 0 && var < NR && __builtin_popcount(var) <= kw; break;
-                case OP_MULTI1: ok = var > 0 && var < NR; break;
+                case OP_MULTI1: case OP_ROT: ok = var > 0 && var < NR; break;
                 case OP_MFMA:
                     ok = bm && r == 5 && (var == 15 || var == 23 || var == 27 || var == 29 || var == 30 || var == 31);
                     break;
@@ -1187,7 +1365,8 @@ void encode_plan(Plan *p)
                     w.push_back(0);
                     continue;
                 }
-                if (op.kind == OP_DENSE || op.kind == OP_MULTI1) {
+                if (op.kind == OP_DENSE || op.kind == OP_MULTI1 || op.kind == OP_ROT) {
+                    // rotations: (a, b) per register bit in the real and imaginary slots
                     for (const cplx &z : op.m) { p->h_mats.push_back(z.real()); p->h_mats.push_back(z.imag()); }
                     w.push_back(op.kind | (op.regmask << 8) | (op.k << 16));
                     w.push_back((int32_t)(uint32_t)(moff & 0xffffffff));
@@ -1336,7 +1515,7 @@ std::string dump_plan(const Plan &p)
                     for (int j = 0; j < op.k; ++j) os << " " << op.tl[j];
                     os << " " << op.m[0].real() << " " << op.m[0].imag();
                 } else {
-                    os << (op.kind == OP_MULTI1 ? "M" : "U") << op.k;
+                    os << (op.kind == OP_MULTI1 ? "M" : op.kind == OP_ROT ? "R" : "U") << op.k;
                     for (int j = 0; j < p.r; ++j)
                         if (op.regmask >> j & 1) os << " " << ph.lay.R[j];
                 }

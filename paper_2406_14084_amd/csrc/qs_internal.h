@@ -33,7 +33,9 @@ enum OpKind {
     OP_SIGN_REG = 4,   //   entries all +-1, bits in registers: bit m of a mask negates register m
     OP_SIGN_ROW = 5,   //   entries all +-1 with thread bits: one such mask per row
     OP_MULTI1 = 6,     // one 2x2 gate on each register bit of regmask (they commute), ascending bit order
-    OP_MFMA = 7        // encoding of a complex64 dense op of k >= 4 register bits run on matrix cores
+    OP_MFMA = 7,       // encoding of a complex64 dense op of k >= 4 register bits run on matrix cores
+    OP_ROT = 8         // a real plane rotation on each register bit of regmask, as three shears
+                       // x0 += a x1, x1 += b x0, x0 += a x1 (coefficients (a, b) per bit, ascending)
 };
 
 struct Op {

@@ -34,7 +34,8 @@ class Circuit_C(C.Structure):
 class PlanOpts_C(C.Structure):
     _fields_ = [("chunk_qubits", C.c_int), ("low_qubits", C.c_int), ("enable_swaps", C.c_int),
                 ("enable_fusion", C.c_int), ("planner", C.c_int), ("cost_model", C.c_void_p),
-                ("dtype", C.c_int), ("reg_qubits", C.c_int), ("no_mfma", C.c_int)]
+                ("dtype", C.c_int), ("reg_qubits", C.c_int), ("no_mfma", C.c_int),
+                ("no_split", C.c_int)]
 
 
 class Pauli_C(C.Structure):
@@ -47,7 +48,8 @@ class PlanStats_C(C.Structure):
                 ("phases", C.c_int), ("chunk_qubits", C.c_int), ("low_qubits", C.c_int), ("reg_qubits", C.c_int),
                 ("flops_per_amp", C.c_double), ("hbm_bytes", C.c_double), ("plan_seconds", C.c_double),
                 ("planner", C.c_int), ("candidates", C.c_int), ("predicted_ms", C.c_double),
-                ("predicted_heuristic_ms", C.c_double), ("ops_mfma", C.c_int)]
+                ("predicted_heuristic_ms", C.c_double), ("ops_mfma", C.c_int),
+                ("ops_rot", C.c_int)]
 
 
 class QaoaInst_C(C.Structure):
@@ -230,14 +232,14 @@ class Plan:
     .n and .arrays())."""
 
     def __init__(self, circuit, kmax=5, dtype="c128", chunk_qubits=0, low_qubits=0, swaps=True, fusion=True,
-                 planner=0, cost_model=None, reg_qubits=0, mfma=True):
+                 planner=0, cost_model=None, reg_qubits=0, mfma=True, split=True):
         k, t, m = circuit.arrays()
         self._keep = (k, t, m)
         circ = Circuit_C(circuit.n, len(k), _ip(k), _ip(t), _dp(m))
         opts = PlanOpts_C(chunk_qubits, low_qubits, int(swaps), int(fusion), planner,
                           cost_model.h if cost_model is not None else None,
                           QS_C64 if dtype in ("c64", "complex64", QS_C64) else QS_C128, reg_qubits,
-                          0 if mfma else 1)
+                          0 if mfma else 1, 0 if split else 1)
         h = C.c_void_p()
         check(lib().qs_fuse(C.byref(circ), kmax, C.byref(opts), C.byref(h)))
         self.h = h

@@ -8,6 +8,15 @@ product of 2^(k+1) terms, so its error is at most
 times the 2-norm of its input (the u term covers the single rounding of the
 matrix to FP32, the 2^(k/2) bounds the 2-norm of |U| for unitary U); a
 diagonal op costs eps_diag = sqrt(2) gamma_2 + u; a +-1 diagonal costs 0.
+A single-qubit gate split into phase * rotation * phase has two diagonal ops
+and one rotation run as three shears S_a S_b S_a (|a|, |b| <= 1, so every
+shear has 2-norm <= phi = (1 + sqrt 5) / 2): rounding a and b to FP32 moves
+the product by <= 3 phi^2 u, and each shear's single FMA rounding (at most
+u sqrt(2) times the norm of the vector it acts on, then carried through the
+remaining shears) adds <= 3 sqrt(2) phi^2 u, so
+    eps_rot = 3 phi^2 (1 + sqrt 2) u (1 + 1e-4) + 2e-14
+per rotated qubit (the last term covers the FP64 factorisation, accepted only
+when it reproduces the gate to 1e-14 per entry).
 Errors of successive (near-)unitary ops add to first order, so
     ||psi_c64 - psi_exact||_2 <= sum over ops of eps_op   (rigorous bound),
 and max|delta amp| <= ||delta||_2, 1 - fidelity <= ||delta||_2^2.
@@ -40,6 +49,8 @@ def eps_dense(k):
 
 
 EPS_DIAG = math.sqrt(2) * gamma(2) + U32
+PHI = (1 + math.sqrt(5)) / 2
+EPS_ROT = 3 * PHI ** 2 * (1 + math.sqrt(2)) * U32 * (1 + 1e-4) + 2e-14
 
 
 def bound_for(plan):
@@ -48,6 +59,7 @@ def bound_for(plan):
     for k in range(1, 6):
         terms += [eps_dense(k)] * s["ops_dense"][k]
     terms += [EPS_DIAG] * s["ops_diag"]
+    terms += [EPS_ROT] * s["ops_rot"]
     return sum(terms), math.sqrt(sum(t * t for t in terms))
 
 

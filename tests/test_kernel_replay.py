@@ -221,6 +221,22 @@ def replay_block(psi, w, n, R, mats, c64=False):
                         out[:, :, cols] = np.einsum("rc,wtc->wtr", M, v[:, :, cols])
                     v = out
                     idx += 1
+            elif kind == 8:       # real rotation per register bit, as three shears, ascending
+                idx = 0
+                for j in range(R):
+                    if not (variant >> j) & 1:
+                        continue
+                    a, b = float(mats[moff + 2 * idx]), float(mats[moff + 2 * idx + 1])
+                    assert abs(a) <= 1 and abs(b) <= 1
+                    lo = [m for m in range(NR) if not (m >> j) & 1]
+                    hi = [m | (1 << j) for m in lo]
+                    x0, x1 = v[:, :, lo].copy(), v[:, :, hi].copy()
+                    x0 = x0 + a * x1
+                    x1 = x1 + b * x0
+                    x0 = x0 + a * x1
+                    v = v.copy()
+                    v[:, :, lo], v[:, :, hi] = x0, x1
+                    idx += 1
             elif kind == 2:       # register diagonal: uniform entry per register
                 E = mats[moff:moff + 2 * NR].view(np.complex128)
                 v = v * E[None, None, :]
@@ -342,7 +358,9 @@ def test_replay_covers_folded_swaps_and_swap_passes():
 
 def test_replay_uses_every_diagonal_encoding():
     """Circuits with general and +-1 diagonals exercise the register, row and
-    sign encodings of diagonal ops."""
+    sign encodings of diagonal ops; with single-qubit gates split (phase,
+    rotation, phase) and kept whole, also the rotation and grouped
+    single-qubit encodings."""
     n = 13
     kinds = set()
     for seed in range(4):
@@ -353,10 +371,11 @@ def test_replay_uses_every_diagonal_encoding():
             c.add("RZZ", (a, b), I.g_rzz(float(rng.uniform(0, 6))))
         c2 = I.random_dense(9, 60, 50 + seed, kmax=3, kinds=("dense", "diag"))
         for cc in (c, c2):
-            p = qs.Plan(cc, kmax=4)
-            kinds |= _op_kinds(p)
-            assert np.max(np.abs(replay_plan(p, cc.n) - sim.run(cc))) <= 1e-12
-    assert {0, 2, 3, 4, 5, 6} <= kinds, kinds
+            for split in (True, False):
+                p = qs.Plan(cc, kmax=4, split=split)
+                kinds |= _op_kinds(p)
+                assert np.max(np.abs(replay_plan(p, cc.n) - sim.run(cc))) <= 1e-12
+    assert {0, 2, 3, 4, 5, 6, 8} <= kinds, kinds
 
 
 def _op_kinds(p):

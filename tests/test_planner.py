@@ -110,11 +110,17 @@ def test_worked_example_fused_diagonal_value():
 
 
 def test_fusion_reduces_or_keeps_cost():
+    """Fusion never adds ops or arithmetic; splitting single-qubit gates into
+    phase * rotation * phase may add (cheap diagonal) ops but lowers the
+    arithmetic further."""
     c = I.random_u3_2q(n=20, depth=20, seed=5)
-    on = qs.Plan(c, kmax=4, fusion=True).stats()
+    on = qs.Plan(c, kmax=4, fusion=True, split=False).stats()
     off = qs.Plan(c, kmax=4, fusion=False).stats()
+    sp = qs.Plan(c, kmax=4, fusion=True).stats()
     assert on["ops"] <= off["ops"]
     assert on["flops_per_amp"] <= off["flops_per_amp"] + 1e-9
+    assert sp["ops_rot"] > 0 and sp["ops_dense"][1] == 0
+    assert sp["flops_per_amp"] < 0.6 * on["flops_per_amp"]
 
 
 def test_gbg_planner_one_block_per_gate():
@@ -186,7 +192,8 @@ def test_block_features_consistent(gen, opts):
     cnt = lambda col, scale: int(round(float((f[:, col].astype(np.float64) * scale).sum())))
     for k in range(2, 6):
         assert cnt(10 + k, 8) == s["ops_dense"][k], k
-    assert cnt(11, 8) + cnt(21, 16) == s["ops_dense"][1]
+    # single-qubit gates: ungrouped dense ops plus grouped ones (dense 2x2 or split-off rotations)
+    assert cnt(11, 8) + cnt(21, 16) == s["ops_dense"][1] + s["ops_rot"]
     assert cnt(16, 8) + cnt(17, 8) + cnt(18, 8) + cnt(19, 8) == s["ops_diag"]
     sign_ops = cnt(18, 8) + cnt(19, 8)
     # stats price every diagonal at 6 flops per amplitude; +-1 diagonals cost none in the features
