@@ -532,12 +532,16 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
                 // read through the constant address space: uniform loads of coefficients
                 // become scalar (SMEM) loads instead of per-lane vector loads
                 const CF *M = (const CF *)(uintptr_t)(mats + ((int64_t)mlo | ((int64_t)mhi << 32)));
+                // KMAX == 0: a block of rotations and diagonals only (no dense paths
+                // compiled in: less code and fewer registers)
                 if (kind == OP_MULTI1) {
-                    multi1_dispatch<R, F, V, const CF *>(variant, v, M);
+                    if constexpr (KMAX > 0) multi1_dispatch<R, F, V, const CF *>(variant, v, M);
+                    else __builtin_unreachable();
                 } else if (kind == OP_ROT) {
                     rot_dispatch<R, F, V, const CF *>(variant, v, M);
                 } else if (kind == OP_DENSE) {
-                    dense_dispatch<R, KMAX, F, V, const CF *>(variant, v, M);
+                    if constexpr (KMAX > 0) dense_dispatch<R, KMAX, F, V, const CF *>(variant, v, M);
+                    else __builtin_unreachable();
                 } else if (kind == OP_SIGN_ROW) {
                     const uint32_t row = pext_u32(tid, (uint32_t)op[1]);
                     const uint32_t s = (uint32_t)ltab[op[3] + row];
@@ -563,17 +567,22 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
                     }
                 } else {   // this lane's row of the op's table (LDS, or device memory)
                     const uint32_t row = pext_u32(tid, (uint32_t)op[1]);
-                    const V *E = variant ? reinterpret_cast<const V *>(
-                                               mats + ((int64_t)(uint32_t)op[2] | ((int64_t)op[3] << 32))) +
-                                               (size_t)row * NR
-                                         : reinterpret_cast<const V *>(ltab + op[3]) + (size_t)row * NR;
+                    auto apply_row = [&](const V *__restrict__ E) __attribute__((always_inline)) {
 #pragma unroll
-                    for (int m = 0; m < NR; ++m) {
-                        const V e = E[m];
-                        v[m] = cmul<F, V>(e.x, e.y, v[m]);
-                        // keep at most four table reads in flight (register pressure)
-                        if ((m & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-                    }
+                        for (int m = 0; m < NR; ++m) {
+                            const V e = E[m];
+                            v[m] = cmul<F, V>(e.x, e.y, v[m]);
+                            // keep at most four table reads in flight (register pressure)
+                            if ((m & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+                        }
+                    };
+                    // two separate paths, so the LDS one is plain LDS reads (a pointer that
+                    // may be either would become flat loads, waited on with the memory counter)
+                    if (variant)
+                        apply_row(reinterpret_cast<const V *>(mats + ((int64_t)(uint32_t)op[2] | ((int64_t)op[3] << 32))) +
+                                  (size_t)row * NR);
+                    else
+                        apply_row(reinterpret_cast<const V *>(ltab + op[3]) + (size_t)row * NR);
                 }
             }
             prev = ph;
@@ -604,10 +613,11 @@ hipError_t launch_RK(qs_state *st, const int *d_prog, const F *d_mats, int C, si
     return hipGetLastError();
 }
 
-// Kernel variant by the widest vector dense op of the block (2, 3 or R
-// register bits; fewer compiled-in cases keep register pressure and with it
-// occupancy in check), plus the matrix-core variant for complex64 blocks
-// with 4-5-qubit ops (vector ops up to 3 bits beside them).
+// Kernel variant by the widest vector dense op of the block (none -- rotations
+// and diagonals only --, 2, 3 or R register bits; fewer compiled-in cases keep
+// register pressure and with it occupancy in check), plus the matrix-core
+// variant for complex64 blocks with 4-5-qubit ops (vector ops up to 3 bits
+// beside them).
 template <int R, typename F>
 hipError_t launch_R(qs_state *st, const int *d_prog, const F *d_mats, int C, size_t tab, int kmax, bool mfma)
 {
@@ -615,6 +625,7 @@ hipError_t launch_R(qs_state *st, const int *d_prog, const F *d_mats, int C, siz
         if (mfma) return launch_RK<5, 3, float, true>(st, d_prog, d_mats, C, tab);
     }
     if (mfma) return hipErrorInvalidValue;
+    if (kmax == 0) return launch_RK<R, 0, F, false>(st, d_prog, d_mats, C, tab);
     if (kmax <= 2 || R <= 2) return launch_RK<R, (R < 2 ? R : 2), F, false>(st, d_prog, d_mats, C, tab);
     if (kmax == 3 || R == 3) return launch_RK<R, 3, F, false>(st, d_prog, d_mats, C, tab);
     return launch_RK<R, R, F, false>(st, d_prog, d_mats, C, tab);

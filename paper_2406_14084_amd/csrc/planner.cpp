@@ -1228,7 +1228,7 @@ static void check_program(const Plan &p)
         const int bk = p.block_kmax[b];
         const bool bm = p.block_mfma[b] != 0;
         // the dense width compiled into the variant the launcher picks
-        const int kw = bm ? 3 : (bk <= 2 || r <= 2) ? std::min(r, 2) : (bk == 3 || r == 3) ? 3 : r;
+        const int kw = bm ? 3 : bk == 0 ? 0 : (bk <= 2 || r <= 2) ? std::min(r, 2) : (bk == 3 || r == 3) ? 3 : r;
         const int32_t *ph = w + PROG_HDR + 2 * C;
         for (int q = 0; q < w[0]; ++q) {
             const int32_t *op = ph + PHASE_HDR + C + 2 * tb + 2 * NR;
@@ -1237,7 +1237,8 @@ static void check_program(const Plan &p)
                 bool ok;
                 switch (kind) {
                 case OP_DENSE: ok = var > 0 && var < NR && __builtin_popcount(var) <= kw; break;
-                case OP_MULTI1: case OP_ROT: ok = var > 0 && var < NR; break;
+                case OP_MULTI1: ok = kw >= 1 && var > 0 && var < NR; break;
+                case OP_ROT: ok = var > 0 && var < NR; break;
                 case OP_MFMA:
                     ok = bm && r == 5 && (var == 15 || var == 23 || var == 27 || var == 29 || var == 30 || var == 31);
                     break;
