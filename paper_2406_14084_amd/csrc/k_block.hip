@@ -521,7 +521,8 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
             }
             // ---- ops of this phase
             const int *op = X + 2 * tb + 2 * NR;
-            for (int o = 0; o < nops; ++o, op += OP_WORDS) {
+            // one op: its kind and register mask select a compile-time code path
+            auto run_op = [&](const int *__restrict__ op) __attribute__((always_inline)) {
                 const int w0 = op[0];
                 const int kind = w0 & 0xff;
                 const int variant = (w0 >> 8) & 0xff;
@@ -584,6 +585,17 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
                     else
                         apply_row(reinterpret_cast<const V *>(ltab + op[3]) + (size_t)row * NR);
                 }
+            };
+            if constexpr (KMAX == 0) {
+                // blocks of rotations and diagonals (small code): two ops per trip, so
+                // that results alternate between two register sets instead of being
+                // copied back into one after every op (phases hold an even op count)
+                for (int o = 0; o < nops; o += 2, op += 2 * OP_WORDS) {
+                    run_op(op);
+                    run_op(op + OP_WORDS);
+                }
+            } else {
+                for (int o = 0; o < nops; ++o, op += OP_WORDS) run_op(op);
             }
             prev = ph;
             ph = op;

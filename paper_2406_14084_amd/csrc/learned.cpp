@@ -88,7 +88,11 @@ void block_features(const Plan &p, std::vector<float> *out)
                     break;
                 case OP_DIAG_REG: ++ndiag_reg; flops += 6; diag_bits += k; break;
                 case OP_DIAG_ROW: ++ndiag_row; flops += 6; diag_bits += k; break;
-                case OP_SIGN_REG: ++nsign_reg; diag_bits += k; break;
+                case OP_SIGN_REG:
+                    if (k == 0) break;      // padding no-op
+                    ++nsign_reg;
+                    diag_bits += k;
+                    break;
                 case OP_SIGN_ROW: ++nsign_row; diag_bits += k; break;
                 default: break;
                 }

@@ -1231,6 +1231,8 @@ static void check_program(const Plan &p)
         const int kw = bm ? 3 : bk == 0 ? 0 : (bk <= 2 || r <= 2) ? std::min(r, 2) : (bk == 3 || r == 3) ? 3 : r;
         const int32_t *ph = w + PROG_HDR + 2 * C;
         for (int q = 0; q < w[0]; ++q) {
+            if (kw == 0 && !bm && (ph[0] & 1))
+                throw std::logic_error("odd op count in a phase of a block without dense ops");
             const int32_t *op = ph + PHASE_HDR + C + 2 * tb + 2 * NR;
             for (int o = 0; o < ph[0]; ++o, op += OP_WORDS) {
                 const int kind = op[0] & 0xff, var = (op[0] >> 8) & 0xff;
@@ -1340,6 +1342,15 @@ void encode_plan(Plan *p)
                         if (m >> j & 1) lr |= 1u << P.lay.R[j];
                     w.push_back(has ? (int32_t)(sw(lr) * amp_bytes) : 0);
                 }
+            }
+            // blocks without dense ops run two ops per loop trip: an odd phase gets a
+            // leading no-op (a sign op with an empty mask)
+            if (bk == 0 && !bm && (P.ops.size() & 1)) {
+                w[hdr] = (int32_t)P.ops.size() + 1;
+                w.push_back(OP_SIGN_REG);
+                w.push_back(0);
+                w.push_back(0);
+                w.push_back(0);
             }
             for (const Op &op : P.ops) {
                 int64_t moff = (int64_t)p->h_mats.size();
