@@ -125,6 +125,26 @@ def test_u3_cz_22q_vs_oracle(torch):
     assert d <= TOL_C128, (d, p.stats())
 
 
+@pytest.mark.parametrize("gen,kmax,reg", [
+    (lambda: I.random_u3_2q(n=22, depth=40, seed=22002), 5, 0),
+    (lambda: I.layered_rotations(n=18, layers=12, seed=18001), 4, 0),
+    (lambda: I.random_u3_2q(n=20, depth=30, seed=20007, two="CX"), 3, 3),
+])
+def test_single_qubit_split_and_whole(torch, gen, kmax, reg):
+    """Single-qubit gates split (phase, shear rotation, phase) and kept whole
+    (grouped 2x2 products) both match the oracle; the split plan has rotation
+    ops and no single-qubit dense ops, the other the reverse."""
+    c = gen()
+    want = sim.run(c)
+    for split in (True, False):
+        say("split" if split else "whole", c.n, kmax, reg)
+        got, p = run_plan(c, kmax=kmax, reg_qubits=reg, split=split)
+        s = p.stats()
+        assert (s["ops_rot"] > 0) == split and (s["ops_dense"][1] == 0 or not split)
+        d = max_abs_diff(got, want)
+        assert d <= TOL_C128, (split, d, s)
+
+
 def test_qft_closed_form_gpu(torch):
     n = 18
     x = 98765

@@ -378,6 +378,20 @@ def test_replay_uses_every_diagonal_encoding():
     assert {0, 2, 3, 4, 5, 6, 8} <= kinds, kinds
 
 
+def test_split_needs_a_unitary_gate():
+    """Only gates that the phase * rotation * phase factorisation reproduces
+    are split: a non-unitary single-qubit matrix stays a dense op, and the
+    replayed state (unitary and non-unitary gates mixed) equals the oracle's."""
+    n = 9
+    c = I.random_u3_2q(n=n, depth=4, seed=41)
+    c.add("M", (3,), np.array([[1.0, 0.0], [0.5, 1.0]], dtype=np.complex128))
+    c.add("M", (5,), np.array([[0.6, 0.8j], [0.8j, 0.6]], dtype=np.complex128))   # unitary
+    p = qs.Plan(c, kmax=3)
+    s = p.stats()
+    assert s["ops_dense"][1] == 1 and s["ops_rot"] >= 1 + n * 4
+    assert np.max(np.abs(replay_plan(p, n) - sim.run(c))) <= 1e-12
+
+
 def _op_kinds(p):
     kinds = set()
     w, offs, R, C, mats = p.program()
