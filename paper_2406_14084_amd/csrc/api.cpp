@@ -157,7 +157,7 @@ static qs_status run_blocks(qs_state *st, const qs::Plan &p, const int *d_prog, 
     for (size_t b = 0; b < p.blocks.size(); ++b) {
         const size_t tab = (size_t)p.h_prog[p.prog_off[b] + 5] * 4;
         hipError_t e = qs::launch_block_prog(st, p.r, p.C, d_prog + p.prog_off[b], d_mats, tab, p.block_kmax[b],
-                                             p.block_mfma[b] != 0);
+                                             p.block_mfma[b] != 0, (p.h_prog[p.prog_off[b] + 3] & 4) != 0);
         if (e != hipSuccess) return hip_fail(e, fn);
     }
     return QS_OK;

@@ -440,7 +440,9 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
     for (int b = 0; b < C; ++b) cmask |= 1ull << Pin[b];
 
     // per-lane data of diagonal ops: staged once into LDS, after the exchange buffer
-    int *ltab = reinterpret_cast<int *>(lds_raw + ((size_t)sizeof(V) << C));
+    // (half the chunk when every exchange of the block runs in two rounds)
+    const bool half = (flags & 4) != 0;
+    int *ltab = reinterpret_cast<int *>(lds_raw + ((size_t)sizeof(V) << (half ? C - 1 : C)));
     {
         const int tab_off = prog[4], tab_words = prog[5];
         for (int i = (int)tid; i < tab_words; i += (int)blockDim.x) ltab[i] = prog[tab_off + i];
@@ -495,7 +497,8 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
                 // per-lane condition around the loads makes the compiler issue and wait
                 // for them one at a time
                 uint32_t wt = 0, rt = 0;
-                const int xt = ph[3];
+                const int xt = ph[3] & 0xffffff;
+                const int hj = (ph[3] >> 24) - 1;      // split thread bit (half-buffer rounds), or -1
                 if (xt > 0) {
                     const int *Xl = ltab + (xt - 1);    // the same words, staged in LDS
                     for (int j = 0; j < tb; ++j) {
@@ -512,12 +515,32 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
                 }
                 const int *wo = X + 2 * tb;
                 const int *ro = wo + NR;
-                lds_barrier();      // previous readers of the buffer are done
+                if (hj < 0) {
+                    lds_barrier();      // previous readers of the buffer are done
 #pragma unroll
-                for (int m = 0; m < NR; ++m) *reinterpret_cast<V *>(lds_raw + (wt ^ (uint32_t)wo[m])) = v[m];
-                lds_barrier();      // every write is visible
+                    for (int m = 0; m < NR; ++m) *reinterpret_cast<V *>(lds_raw + (wt ^ (uint32_t)wo[m])) = v[m];
+                    lds_barrier();      // every write is visible
 #pragma unroll
-                for (int m = 0; m < NR; ++m) v[m] = *reinterpret_cast<const V *>(lds_raw + (rt ^ (uint32_t)ro[m]));
+                    for (int m = 0; m < NR; ++m) v[m] = *reinterpret_cast<const V *>(lds_raw + (rt ^ (uint32_t)ro[m]));
+                } else {
+                    // two rounds through half the buffer: the threads whose bit hj is h
+                    // hold (before and after) exactly the amplitudes of one half
+                    const uint32_t mine = (tid >> hj) & 1u;
+                    for (uint32_t h = 0; h < 2; ++h) {
+                        lds_barrier();
+                        if (mine == h) {
+#pragma unroll
+                            for (int m = 0; m < NR; ++m)
+                                *reinterpret_cast<V *>(lds_raw + (wt ^ (uint32_t)wo[m])) = v[m];
+                        }
+                        lds_barrier();
+                        if (mine == h) {
+#pragma unroll
+                            for (int m = 0; m < NR; ++m)
+                                v[m] = *reinterpret_cast<const V *>(lds_raw + (rt ^ (uint32_t)ro[m]));
+                        }
+                    }
+                }
             }
             // ---- ops of this phase
             const int *op = X + 2 * tb + 2 * NR;
@@ -606,10 +629,10 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
 }
 
 template <int R, int KMAX, typename F, bool MF>
-hipError_t launch_RK(qs_state *st, const int *d_prog, const F *d_mats, int C, size_t tab_bytes)
+hipError_t launch_RK(qs_state *st, const int *d_prog, const F *d_mats, int C, size_t tab_bytes, bool half)
 {
     using V = typename AmpOf<F>::type;
-    const size_t lds = ((size_t)1 << C) * sizeof(V) + ((tab_bytes + 15) & ~(size_t)15);
+    const size_t lds = ((size_t)1 << (half ? C - 1 : C)) * sizeof(V) + ((tab_bytes + 15) & ~(size_t)15);
     if (lds > 160u * 1024u) return hipErrorInvalidValue;
     auto kern = k_block<R, KMAX, F, MF>;
     static bool attr_set = false;
@@ -631,27 +654,30 @@ hipError_t launch_RK(qs_state *st, const int *d_prog, const F *d_mats, int C, si
 // variant for complex64 blocks with 4-5-qubit ops (vector ops up to 3 bits
 // beside them).
 template <int R, typename F>
-hipError_t launch_R(qs_state *st, const int *d_prog, const F *d_mats, int C, size_t tab, int kmax, bool mfma)
+hipError_t launch_R(qs_state *st, const int *d_prog, const F *d_mats, int C, size_t tab, int kmax, bool mfma, bool half)
 {
+    // half-buffer exchanges exist only in blocks of rotations and diagonals
+    if (half && (mfma || kmax != 0)) return hipErrorInvalidValue;
     if constexpr (R == 5 && std::is_same<F, float>::value) {
-        if (mfma) return launch_RK<5, 3, float, true>(st, d_prog, d_mats, C, tab);
+        if (mfma) return launch_RK<5, 3, float, true>(st, d_prog, d_mats, C, tab, false);
     }
     if (mfma) return hipErrorInvalidValue;
-    if (kmax == 0) return launch_RK<R, 0, F, false>(st, d_prog, d_mats, C, tab);
-    if (kmax <= 2 || R <= 2) return launch_RK<R, (R < 2 ? R : 2), F, false>(st, d_prog, d_mats, C, tab);
-    if (kmax == 3 || R == 3) return launch_RK<R, 3, F, false>(st, d_prog, d_mats, C, tab);
-    return launch_RK<R, R, F, false>(st, d_prog, d_mats, C, tab);
+    if (kmax == 0) return launch_RK<R, 0, F, false>(st, d_prog, d_mats, C, tab, half);
+    if (kmax <= 2 || R <= 2) return launch_RK<R, (R < 2 ? R : 2), F, false>(st, d_prog, d_mats, C, tab, half);
+    if (kmax == 3 || R == 3) return launch_RK<R, 3, F, false>(st, d_prog, d_mats, C, tab, half);
+    return launch_RK<R, R, F, false>(st, d_prog, d_mats, C, tab, half);
 }
 
 template <typename F>
-hipError_t launch_F(qs_state *st, int r, const int *d_prog, const F *d_mats, int C, size_t tab, int kmax, bool mfma)
+hipError_t launch_F(qs_state *st, int r, const int *d_prog, const F *d_mats, int C, size_t tab, int kmax, bool mfma,
+                    bool half)
 {
     switch (r) {
-    case 1: return launch_R<1, F>(st, d_prog, d_mats, C, tab, kmax, mfma);
-    case 2: return launch_R<2, F>(st, d_prog, d_mats, C, tab, kmax, mfma);
-    case 3: return launch_R<3, F>(st, d_prog, d_mats, C, tab, kmax, mfma);
-    case 4: return launch_R<4, F>(st, d_prog, d_mats, C, tab, kmax, mfma);
-    case 5: return launch_R<5, F>(st, d_prog, d_mats, C, tab, kmax, mfma);
+    case 1: return launch_R<1, F>(st, d_prog, d_mats, C, tab, kmax, mfma, half);
+    case 2: return launch_R<2, F>(st, d_prog, d_mats, C, tab, kmax, mfma, half);
+    case 3: return launch_R<3, F>(st, d_prog, d_mats, C, tab, kmax, mfma, half);
+    case 4: return launch_R<4, F>(st, d_prog, d_mats, C, tab, kmax, mfma, half);
+    case 5: return launch_R<5, F>(st, d_prog, d_mats, C, tab, kmax, mfma, half);
     default: return hipErrorInvalidValue;
     }
 }
@@ -659,21 +685,24 @@ hipError_t launch_F(qs_state *st, int r, const int *d_prog, const F *d_mats, int
 }  // namespace
 
 hipError_t launch_block_prog(qs_state *st, int r, int C, const int *d_prog, const void *d_mats, size_t tab_bytes,
-                             int kmax_dense, bool mfma)
+                             int kmax_dense, bool mfma, bool half)
 {
     if (C < r || st->n < C || (1 << (C - r)) > (r <= 3 ? 512 : 256)) return hipErrorInvalidValue;
     // matrix-core ops stage each wave's amplitudes in its own slice of the chunk buffer
     if (mfma && (st->dtype != QS_C64 || r != 5 || C - r < 6)) return hipErrorInvalidValue;
     if (st->dtype == QS_C64)
-        return launch_F<float>(st, r, d_prog, reinterpret_cast<const float *>(d_mats), C, tab_bytes, kmax_dense, mfma);
-    return launch_F<double>(st, r, d_prog, reinterpret_cast<const double *>(d_mats), C, tab_bytes, kmax_dense, mfma);
+        return launch_F<float>(st, r, d_prog, reinterpret_cast<const float *>(d_mats), C, tab_bytes, kmax_dense, mfma,
+                               half);
+    return launch_F<double>(st, r, d_prog, reinterpret_cast<const double *>(d_mats), C, tab_bytes, kmax_dense, mfma,
+                            half);
 }
 
 hipError_t launch_block(qs_state *st, const Plan &p, int b)
 {
     const int *prog = reinterpret_cast<const int *>(p.d_prog) + p.prog_off[b];
     const size_t tab_bytes = (size_t)p.h_prog[p.prog_off[b] + 5] * 4;
-    return launch_block_prog(st, p.r, p.C, prog, p.d_mats, tab_bytes, p.block_kmax[b], p.block_mfma[b] != 0);
+    const bool half = (p.h_prog[p.prog_off[b] + 3] & 4) != 0;
+    return launch_block_prog(st, p.r, p.C, prog, p.d_mats, tab_bytes, p.block_kmax[b], p.block_mfma[b] != 0, half);
 }
 
 }  // namespace qs

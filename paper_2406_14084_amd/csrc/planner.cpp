@@ -694,6 +694,38 @@ Layout make_layout(uint32_t Rmask, int C, int r, const std::vector<int> *store_o
 }
 
 
+// Layout of a later phase of a block: register bits R; thread positions keep
+// the previous layout's bit wherever it is still a thread bit (an exchange then
+// moves as few thread positions as possible, which lets it run through half
+// the LDS buffer, see encode_plan), except the first low.size() positions,
+// which take the given bits (the store layout's output-low bits: coalesced
+// stores); the rest ascending.
+Layout make_layout_keep(uint32_t Rmask, int C, int r, const Layout &prev, const std::vector<int> &low)
+{
+    Layout lay;
+    int i = 0;
+    for (int b = 0; b < C; ++b)
+        if (Rmask >> b & 1) lay.R[i++] = b;
+    const int tb = C - r;
+    std::vector<int> T(tb, -1);
+    std::vector<char> placed(C, 0);
+    int k0 = 0;
+    for (int b : low) { T[k0++] = b; placed[b] = 1; }
+    for (int j = k0; j < tb; ++j) {
+        const int b = prev.T[j];
+        if (!(Rmask >> b & 1) && !placed[b]) { T[j] = b; placed[b] = 1; }
+    }
+    int b = 0;
+    for (int j = 0; j < tb; ++j) {
+        if (T[j] >= 0) continue;
+        while (b < C && ((Rmask >> b & 1) || placed[b])) ++b;
+        T[j] = b;
+        placed[b] = 1;
+    }
+    for (int j = 0; j < tb; ++j) lay.T[j] = T[j];
+    return lay;
+}
+
 // A pass that only permutes: W = physical positions of the chunk (size C,
 // containing 0..L-1), target_pos[i] = new position of the amplitude bit now at W[i].
 Block make_perm_block(int C, int r, int L, const std::vector<int> &W, const std::vector<int> &target_pos)
@@ -978,6 +1010,7 @@ qs_status build_plan(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan 
         uint32_t lowmask_in = (L > 0) ? ((1u << L) - 1) : 0;      // local bits at physical 0..L-1 on load
         uint32_t lowmask_out = 0;
         for (int i = 0; i < L; ++i) lowmask_out |= 1u << store_order[i];
+        const std::vector<int> low_out(store_order.begin(), store_order.begin() + L);
         uint32_t all = (C >= 32) ? 0xffffffffu : ((1u << C) - 1);
         std::vector<SetOp> prem = ops;
         bool first = true;
@@ -994,7 +1027,8 @@ qs_status build_plan(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan 
                 if (!used[i]) rest.push_back(prem[i]);
             prem.swap(rest);
             Phase ph;
-            ph.lay = make_layout(R, C, r, nullptr);
+            ph.lay = first ? make_layout(R, C, r, nullptr)
+                           : make_layout_keep(R, C, r, blk.phases.back().lay, std::vector<int>());
             std::vector<Op> kops;
             std::vector<SetOp> fused = PS.fuse_phase(phase_ops, R);
             if (opts.enable_fusion) fused = PS.reschedule(fused, R);
@@ -1017,10 +1051,12 @@ qs_status build_plan(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan 
                     if (!(lowmask_out >> b & 1)) { R |= 1u << b; ++cnt; }
                 }
                 Phase sp;
-                sp.lay = make_layout(R, C, r, &store_order);
+                sp.lay = make_layout_keep(R, C, r, lastp.lay, low_out);
                 blk.phases.push_back(sp);
-            } else {
+            } else if (blk.phases.size() == 1) {
                 lastp.lay = make_layout(Rl, C, r, &store_order);
+            } else {
+                lastp.lay = make_layout_keep(Rl, C, r, blk.phases[blk.phases.size() - 2].lay, low_out);
                 // ops of the last phase index registers by R, which is unchanged
             }
         }
@@ -1230,9 +1266,14 @@ static void check_program(const Plan &p)
         // the dense width compiled into the variant the launcher picks
         const int kw = bm ? 3 : bk == 0 ? 0 : (bk <= 2 || r <= 2) ? std::min(r, 2) : (bk == 3 || r == 3) ? 3 : r;
         const int32_t *ph = w + PROG_HDR + 2 * C;
+        if ((w[3] & 4) && !(kw == 0 && !bm))
+            throw std::logic_error("half-buffer exchanges in a block with dense ops");
         for (int q = 0; q < w[0]; ++q) {
             if (kw == 0 && !bm && (ph[0] & 1))
                 throw std::logic_error("odd op count in a phase of a block without dense ops");
+            const int hj = (ph[3] >> 24) - 1;
+            if ((hj >= 0) != (q > 0 && (w[3] & 4) != 0) || hj >= tb)
+                throw std::logic_error("bad half-buffer exchange position");
             const int32_t *op = ph + PHASE_HDR + C + 2 * tb + 2 * NR;
             for (int o = 0; o < ph[0]; ++o, op += OP_WORDS) {
                 const int kind = op[0] & 0xff, var = (op[0] >> 8) & 0xff;
@@ -1283,7 +1324,21 @@ void encode_plan(Plan *p)
         // flags: bit 0 = swap pass; bit 1 = the write-back moves amplitudes between
         // threads' load positions (P_out != P_in), so loads must all complete
         // before any store even when no exchange separates them
-        w.push_back((blk.permute_only ? 1 : 0) | (blk.P_out != blk.P_in ? 2 : 0));
+        // Half-buffer exchanges (blocks of the variant without dense ops): when every
+        // exchange of the block keeps some chunk bit b >= 4 at the same thread
+        // position j in both layouts, each thread's amplitudes all share b's value
+        // before and after, so the exchange runs in two rounds -- threads with
+        // bit j = 0, then 1 -- through a buffer of half the chunk (b dropped from
+        // the LDS addresses).  Less LDS per workgroup, more workgroups per CU.
+        std::vector<int> split_pos(blk.phases.size(), -1);
+        bool half = bk == 0 && !bm && !blk.permute_only && blk.phases.size() >= 2;
+        for (size_t ph = 1; half && ph < blk.phases.size(); ++ph) {
+            const Layout &a = blk.phases[ph - 1].lay, &b2 = blk.phases[ph].lay;
+            for (int j = C - r - 1; j >= 0 && split_pos[ph] < 0; --j)   // wave bits first
+                if (a.T[j] == b2.T[j] && a.T[j] >= 4) split_pos[ph] = j;
+            if (split_pos[ph] < 0) half = false;
+        }
+        w.push_back((blk.permute_only ? 1 : 0) | (blk.P_out != blk.P_in ? 2 : 0) | (half ? 4 : 0));
         w.push_back(0);   // table offset, patched below
         w.push_back(0);   // table words
         w.push_back(0);
@@ -1323,12 +1378,7 @@ void encode_plan(Plan *p)
                 const Layout *pl = has ? &blk.phases[ph - 1].lay : nullptr;
                 for (int j = 0; j < C - r; ++j) w.push_back(has ? (int32_t)(sw(1u << pl->T[j]) * amp_bytes) : 0);
                 for (int j = 0; j < C - r; ++j) w.push_back(has ? (int32_t)(sw(1u << P.lay.T[j]) * amp_bytes) : 0);
-                // a copy of the thread-bit words in the LDS table (header word 3 = its
-                // offset + 1): the kernel reads them per lane without global loads
-                if (has && tab.size() + 2 * (size_t)(C - r) <= tab_cap) {
-                    w[hdr + 3] = (int32_t)tab.size() + 1;
-                    tab.insert(tab.end(), w.end() - 2 * (C - r), w.end());
-                }
+                const size_t xw0 = w.size() - 2 * (size_t)(C - r);   // the thread-bit words
                 for (int m = 0; m < NR; ++m) {
                     uint32_t lr = 0;
                     if (has)
@@ -1341,6 +1391,20 @@ void encode_plan(Plan *p)
                     for (int j = 0; j < r; ++j)
                         if (m >> j & 1) lr |= 1u << P.lay.R[j];
                     w.push_back(has ? (int32_t)(sw(lr) * amp_bytes) : 0);
+                }
+                if (has && half) {
+                    // drop the split bit from every byte address (linear, like the swizzle)
+                    const int bb = P.lay.T[split_pos[ph]] + (amp_bytes == 16 ? 4 : 3);
+                    auto drop = [bb](uint32_t x) { return (x & ((1u << bb) - 1)) | ((x >> (bb + 1)) << bb); };
+                    const size_t x0 = w.size() - 2 * (size_t)(C - r) - 2 * (size_t)NR;
+                    for (size_t i = x0; i < w.size(); ++i) w[i] = (int32_t)drop((uint32_t)w[i]);
+                    w[hdr + 3] |= (split_pos[ph] + 1) << 24;
+                }
+                // a copy of the thread-bit words in the LDS table (header word 3, low 24
+                // bits = its offset + 1): the kernel reads them per lane without global loads
+                if (has && tab.size() + 2 * (size_t)(C - r) <= tab_cap) {
+                    w[hdr + 3] |= (int32_t)tab.size() + 1;
+                    tab.insert(tab.end(), w.begin() + xw0, w.begin() + xw0 + 2 * (C - r));
                 }
             }
             // blocks without dense ops run two ops per loop trip: an odd phase gets a

@@ -180,5 +180,5 @@ hipError_t launch_block(qs_state *st, const Plan &p, int b);
 hipStream_t costmodel_stream(const qs_costmodel *m);
 int costmodel_device(const qs_costmodel *m);
 hipError_t launch_block_prog(qs_state *st, int r, int C, const int *d_prog, const void *d_mats, size_t tab_bytes,
-                             int kmax_dense, bool mfma);
+                             int kmax_dense, bool mfma, bool half);
 }

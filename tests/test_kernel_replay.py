@@ -130,8 +130,9 @@ def replay_block(psi, w, n, R, mats, c64=False):
     ph = PROG_HDR + 2 * C
     tab_off, tab_words = int(w[4]), int(w[5])
     assert tab_off % 4 == 0 and (tab_words == 0 or tab_off >= ph)
-    # the table plus the exchange buffer must fit the 160 KiB of LDS
-    assert ((8 if c64 else 16) << C) + 4 * tab_words <= 160 * 1024
+    # the table plus the exchange buffer (half the chunk in half-buffer blocks) must fit 160 KiB
+    half = (int(w[3]) & 4) != 0
+    assert ((8 if c64 else 16) << (C - 1 if half else C)) + 4 * tab_words <= 160 * 1024
 
     def layout(at):
         Rb = [int(x) for x in w[at + PHASE_HDR:at + PHASE_HDR + R]]
@@ -176,9 +177,19 @@ def replay_block(psi, w, n, R, mats, c64=False):
             for j in range(tb):
                 kw ^= np.where((tid >> j) & 1, xw[j], 0)
                 kr ^= np.where((tid >> j) & 1, xr[j], 0)
-            assert np.array_equal(kw[:, None] ^ wo[None, :], ws * ab)
-            assert np.array_equal(kr[:, None] ^ ro[None, :], rs * ab)
-            xt = int(w[ph + 3])
+            hj = (int(w[ph + 3]) >> 24) - 1
+            assert (hj >= 0) == half
+            if hj >= 0:
+                # split bit: at thread position hj in both layouts, dropped from the addresses
+                assert pT[hj] == T[hj] and T[hj] >= 4
+                bb = T[hj] + (3 if c64 else 4)
+                drop = lambda x: (x & ((1 << bb) - 1)) | ((x >> (bb + 1)) << bb)
+                assert np.array_equal(kw[:, None] ^ wo[None, :], drop(ws * ab))
+                assert np.array_equal(kr[:, None] ^ ro[None, :], drop(rs * ab))
+            else:
+                assert np.array_equal(kw[:, None] ^ wo[None, :], ws * ab)
+                assert np.array_equal(kr[:, None] ^ ro[None, :], rs * ab)
+            xt = int(w[ph + 3]) & 0xffffff
             if xt > 0:   # the kernel reads a copy of the thread-bit words from the LDS table
                 a = xt - 1
                 assert a + 2 * tb <= tab_words
@@ -186,9 +197,23 @@ def replay_block(psi, w, n, R, mats, c64=False):
             for s in (ws, rs):
                 assert s.min() >= 0 and s.max() < (1 << C)
                 assert np.unique(s).size == s.size == (1 << C), "exchange is not a bijection"
-            lds = np.zeros((nwg, 1 << C), dtype=np.complex128)
-            lds[:, ws.reshape(-1)] = v.reshape(nwg, -1)
-            v = lds[:, rs.reshape(-1)].reshape(nwg, 1 << tb, NR)
+            if hj < 0:
+                lds = np.zeros((nwg, 1 << C), dtype=np.complex128)
+                lds[:, ws.reshape(-1)] = v.reshape(nwg, -1)
+                v = lds[:, rs.reshape(-1)].reshape(nwg, 1 << tb, NR)
+            else:
+                # two rounds through half the buffer, as the kernel runs them
+                cw = (kw[:, None] ^ wo[None, :]) // ab
+                cr = (kr[:, None] ^ ro[None, :]) // ab
+                v = v.copy()
+                for h in (0, 1):
+                    sel = ((tid >> hj) & 1) == h
+                    for s in (cw[sel], cr[sel]):
+                        assert s.min() >= 0 and s.max() < (1 << (C - 1))
+                        assert np.unique(s).size == s.size == (1 << (C - 1)), "half round is not a bijection"
+                    lds = np.full((nwg, 1 << (C - 1)), np.nan, dtype=np.complex128)
+                    lds[:, cw[sel].reshape(-1)] = v[:, sel, :].reshape(nwg, -1)
+                    v[:, sel, :] = lds[:, cr[sel].reshape(-1)].reshape(nwg, -1, NR)
         op = ph + PHASE_HDR + C + 2 * tb + 2 * NR
         for _ in range(nops):
             w0 = int(w[op])
@@ -325,9 +350,16 @@ def test_replay_matches_oracle(cfg):
 
 
 def test_replay_u3_cz_and_layered():
-    for c in (I.random_u3_2q(n=14, depth=12, seed=3), I.layered_rotations(n=13, layers=8, seed=4)):
+    """Includes blocks whose exchanges run in two rounds through half the LDS
+    buffer (U3 + CZ: rotations and diagonals only)."""
+    halves = 0
+    for c in (I.random_u3_2q(n=14, depth=12, seed=3), I.layered_rotations(n=13, layers=8, seed=4),
+              I.random_u3_2q(n=16, depth=10, seed=1)):
         p = qs.Plan(c, kmax=5)
+        w, offs, R, C, mats = p.program()
+        halves += sum(1 for o in offs if int(w[o + 3]) & 4)
         assert np.max(np.abs(replay_plan(p, c.n) - sim.run(c))) <= 1e-12
+    assert halves > 0
 
 
 def test_replay_swap_plan_is_bit_permutation():
