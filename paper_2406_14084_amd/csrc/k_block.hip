@@ -498,7 +498,10 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
                 // for them one at a time
                 uint32_t wt = 0, rt = 0;
                 const int xt = ph[3] & 0xffffff;
-                const int hj = (ph[3] >> 24) - 1;      // split thread bit (half-buffer rounds), or -1
+                // half-buffer rounds: thread positions of the split bit in the write and the
+                // read layout (-1: one round through the whole buffer)
+                const uint32_t hx = (uint32_t)ph[3] >> 24;
+                const int hjw = (int)(hx & 15u) - 1, hjr = (int)(hx >> 4) - 1;
                 if (xt > 0) {
                     const int *Xl = ltab + (xt - 1);    // the same words, staged in LDS
                     for (int j = 0; j < tb; ++j) {
@@ -515,7 +518,7 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
                 }
                 const int *wo = X + 2 * tb;
                 const int *ro = wo + NR;
-                if (hj < 0) {
+                if (hjw < 0) {
                     lds_barrier();      // previous readers of the buffer are done
 #pragma unroll
                     for (int m = 0; m < NR; ++m) *reinterpret_cast<V *>(lds_raw + (wt ^ (uint32_t)wo[m])) = v[m];
@@ -523,18 +526,19 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
 #pragma unroll
                     for (int m = 0; m < NR; ++m) v[m] = *reinterpret_cast<const V *>(lds_raw + (rt ^ (uint32_t)ro[m]));
                 } else {
-                    // two rounds through half the buffer: the threads whose bit hj is h
-                    // hold (before and after) exactly the amplitudes of one half
-                    const uint32_t mine = (tid >> hj) & 1u;
+                    // two rounds through half the buffer: the threads whose bit hjw (= hjr, the
+                    // planner keeps the split bit at one position) is h hold exactly the
+                    // amplitudes of half h, before and after; each writes, then reads
+                    const uint32_t mw = (tid >> hjw) & 1u, mr = (tid >> hjr) & 1u;
                     for (uint32_t h = 0; h < 2; ++h) {
                         lds_barrier();
-                        if (mine == h) {
+                        if (mw == h) {
 #pragma unroll
                             for (int m = 0; m < NR; ++m)
                                 *reinterpret_cast<V *>(lds_raw + (wt ^ (uint32_t)wo[m])) = v[m];
                         }
                         lds_barrier();
-                        if (mine == h) {
+                        if (mr == h) {
 #pragma unroll
                             for (int m = 0; m < NR; ++m)
                                 v[m] = *reinterpret_cast<const V *>(lds_raw + (rt ^ (uint32_t)ro[m]));

@@ -1271,8 +1271,9 @@ static void check_program(const Plan &p)
         for (int q = 0; q < w[0]; ++q) {
             if (kw == 0 && !bm && (ph[0] & 1))
                 throw std::logic_error("odd op count in a phase of a block without dense ops");
-            const int hj = (ph[3] >> 24) - 1;
-            if ((hj >= 0) != (q > 0 && (w[3] & 4) != 0) || hj >= tb)
+            const uint32_t hx = (uint32_t)ph[3] >> 24;
+            const int hjw = (int)(hx & 15) - 1, hjr = (int)(hx >> 4) - 1;
+            if ((hjw >= 0) != (q > 0 && (w[3] & 4) != 0) || hjw != hjr || hjw >= tb)
                 throw std::logic_error("bad half-buffer exchange position");
             const int32_t *op = ph + PHASE_HDR + C + 2 * tb + 2 * NR;
             for (int o = 0; o < ph[0]; ++o, op += OP_WORDS) {
@@ -1325,18 +1326,26 @@ void encode_plan(Plan *p)
         // threads' load positions (P_out != P_in), so loads must all complete
         // before any store even when no exchange separates them
         // Half-buffer exchanges (blocks of the variant without dense ops): when every
-        // exchange of the block keeps some chunk bit b >= 4 at the same thread
-        // position j in both layouts, each thread's amplitudes all share b's value
-        // before and after, so the exchange runs in two rounds -- threads with
-        // bit j = 0, then 1 -- through a buffer of half the chunk (b dropped from
-        // the LDS addresses).  Less LDS per workgroup, more workgroups per CU.
-        std::vector<int> split_pos(blk.phases.size(), -1);
+        // exchange of the block has a chunk bit b >= 4 at the same thread position j
+        // in both layouts, each thread's amplitudes all share b's value before and
+        // after, so the exchange runs in two rounds through a buffer of half the
+        // chunk (b dropped from the LDS addresses): in round h the threads with bit
+        // j = h write and, after a barrier, read.  (With b at different positions a
+        // thread could read in round 0 and write in round 1, over registers already
+        // replaced.)  Less LDS per workgroup, more workgroups per CU.  Wave-index
+        // positions are preferred (whole waves take part in a round, no divergence).
+        std::vector<int> split_w(blk.phases.size(), -1), split_r(blk.phases.size(), -1), split_b(blk.phases.size(), -1);
         bool half = bk == 0 && !bm && !blk.permute_only && blk.phases.size() >= 2;
         for (size_t ph = 1; half && ph < blk.phases.size(); ++ph) {
             const Layout &a = blk.phases[ph - 1].lay, &b2 = blk.phases[ph].lay;
-            for (int j = C - r - 1; j >= 0 && split_pos[ph] < 0; --j)   // wave bits first
-                if (a.T[j] == b2.T[j] && a.T[j] >= 4) split_pos[ph] = j;
-            if (split_pos[ph] < 0) half = false;
+            int best = -1;
+            for (int ja = 0; ja < C - r; ++ja)
+                for (int jb = 0; jb < C - r; ++jb) {
+                    if (ja != jb || a.T[ja] != b2.T[jb] || a.T[ja] < 4) continue;
+                    const int score = (ja >= 6) + (jb >= 6) + (ja == jb);
+                    if (score > best) { best = score; split_w[ph] = ja; split_r[ph] = jb; split_b[ph] = a.T[ja]; }
+                }
+            if (best < 0) half = false;
         }
         w.push_back((blk.permute_only ? 1 : 0) | (blk.P_out != blk.P_in ? 2 : 0) | (half ? 4 : 0));
         w.push_back(0);   // table offset, patched below
@@ -1394,11 +1403,11 @@ void encode_plan(Plan *p)
                 }
                 if (has && half) {
                     // drop the split bit from every byte address (linear, like the swizzle)
-                    const int bb = P.lay.T[split_pos[ph]] + (amp_bytes == 16 ? 4 : 3);
+                    const int bb = split_b[ph] + (amp_bytes == 16 ? 4 : 3);
                     auto drop = [bb](uint32_t x) { return (x & ((1u << bb) - 1)) | ((x >> (bb + 1)) << bb); };
                     const size_t x0 = w.size() - 2 * (size_t)(C - r) - 2 * (size_t)NR;
                     for (size_t i = x0; i < w.size(); ++i) w[i] = (int32_t)drop((uint32_t)w[i]);
-                    w[hdr + 3] |= (split_pos[ph] + 1) << 24;
+                    w[hdr + 3] |= (int32_t)((uint32_t)(split_w[ph] + 1) << 24 | (uint32_t)(split_r[ph] + 1) << 28);
                 }
                 // a copy of the thread-bit words in the LDS table (header word 3, low 24
                 // bits = its offset + 1): the kernel reads them per lane without global loads

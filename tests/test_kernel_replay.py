@@ -177,12 +177,13 @@ def replay_block(psi, w, n, R, mats, c64=False):
             for j in range(tb):
                 kw ^= np.where((tid >> j) & 1, xw[j], 0)
                 kr ^= np.where((tid >> j) & 1, xr[j], 0)
-            hj = (int(w[ph + 3]) >> 24) - 1
-            assert (hj >= 0) == half
-            if hj >= 0:
-                # split bit: at thread position hj in both layouts, dropped from the addresses
-                assert pT[hj] == T[hj] and T[hj] >= 4
-                bb = T[hj] + (3 if c64 else 4)
+            hx = int(np.uint32(w[ph + 3])) >> 24
+            hjw, hjr = (hx & 15) - 1, (hx >> 4) - 1
+            assert (hjw >= 0) == half == (hjr >= 0)
+            if hjw >= 0:
+                # split bit: a thread bit in both layouts (positions hjw, hjr), dropped from the addresses
+                assert pT[hjw] == T[hjr] and T[hjr] >= 4
+                bb = T[hjr] + (3 if c64 else 4)
                 drop = lambda x: (x & ((1 << bb) - 1)) | ((x >> (bb + 1)) << bb)
                 assert np.array_equal(kw[:, None] ^ wo[None, :], drop(ws * ab))
                 assert np.array_equal(kr[:, None] ^ ro[None, :], drop(rs * ab))
@@ -197,7 +198,7 @@ def replay_block(psi, w, n, R, mats, c64=False):
             for s in (ws, rs):
                 assert s.min() >= 0 and s.max() < (1 << C)
                 assert np.unique(s).size == s.size == (1 << C), "exchange is not a bijection"
-            if hj < 0:
+            if hjw < 0:
                 lds = np.zeros((nwg, 1 << C), dtype=np.complex128)
                 lds[:, ws.reshape(-1)] = v.reshape(nwg, -1)
                 v = lds[:, rs.reshape(-1)].reshape(nwg, 1 << tb, NR)
@@ -206,14 +207,16 @@ def replay_block(psi, w, n, R, mats, c64=False):
                 cw = (kw[:, None] ^ wo[None, :]) // ab
                 cr = (kr[:, None] ^ ro[None, :]) // ab
                 v = v.copy()
+                # registers are updated in place, round by round, as in the kernel
+                v = v.copy()
                 for h in (0, 1):
-                    sel = ((tid >> hj) & 1) == h
-                    for s in (cw[sel], cr[sel]):
+                    sw_, sr_ = ((tid >> hjw) & 1) == h, ((tid >> hjr) & 1) == h
+                    for s in (cw[sw_], cr[sr_]):
                         assert s.min() >= 0 and s.max() < (1 << (C - 1))
                         assert np.unique(s).size == s.size == (1 << (C - 1)), "half round is not a bijection"
                     lds = np.full((nwg, 1 << (C - 1)), np.nan, dtype=np.complex128)
-                    lds[:, cw[sel].reshape(-1)] = v[:, sel, :].reshape(nwg, -1)
-                    v[:, sel, :] = lds[:, cr[sel].reshape(-1)].reshape(nwg, -1, NR)
+                    lds[:, cw[sw_].reshape(-1)] = v[:, sw_, :].reshape(nwg, -1)
+                    v[:, sr_, :] = lds[:, cr[sr_].reshape(-1)].reshape(nwg, -1, NR)
         op = ph + PHASE_HDR + C + 2 * tb + 2 * NR
         for _ in range(nops):
             w0 = int(w[op])
