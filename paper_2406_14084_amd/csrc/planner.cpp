@@ -1043,12 +1043,23 @@ qs_status build_plan(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan 
             uint32_t Rl = 0;
             for (int j = 0; j < r; ++j) Rl |= 1u << lastp.lay.R[j];
             if ((Rl & lowmask_out) || (blk.phases.size() == 1 && lowmask_out != lowmask_in)) {
-                // choose the r highest output positions that are not low
+                // choose the r highest output positions that are not low, sparing one
+                // chunk bit >= 4 that keeps its (non-low) thread position from the last
+                // phase, so that this exchange too can run through half the LDS buffer
+                int anchor = -1;
+                for (int j = C - r - 1; j >= L && anchor < 0; --j) {
+                    const int b = lastp.lay.T[j];
+                    if (b >= 4 && !(lowmask_out >> b & 1)) anchor = b;
+                }
                 uint32_t R = 0;
                 int cnt = 0;
                 for (int i = C - 1; i >= 0 && cnt < r; --i) {
                     int b = store_order[i];
-                    if (!(lowmask_out >> b & 1)) { R |= 1u << b; ++cnt; }
+                    if (!(lowmask_out >> b & 1) && b != anchor) { R |= 1u << b; ++cnt; }
+                }
+                for (int i = C - 1; i >= 0 && cnt < r; --i) {      // too few bits: use the anchor too
+                    int b = store_order[i];
+                    if (!(lowmask_out >> b & 1) && !(R >> b & 1)) { R |= 1u << b; ++cnt; }
                 }
                 Phase sp;
                 sp.lay = make_layout_keep(R, C, r, lastp.lay, low_out);
