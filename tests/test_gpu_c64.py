@@ -84,6 +84,25 @@ def test_c64_random_vs_oracle(torch, n, seed, kmax):
     assert d2 <= rig
 
 
+def test_c64_u3_cz_20q_half_buffer_vs_oracle(torch):
+    """complex64 U3 + CZ: blocks of shear rotations and diagonals whose
+    exchanges run in two rounds through half the LDS buffer (every block of
+    this plan), within the rigorous bound of the oracle."""
+    c = I.random_u3_2q(n=20, depth=20, seed=2020)
+    say("c64 u3cz20 half-buffer")
+    st = qs.State(20, "c64")
+    st.init_zero()
+    p = qs.Plan(c, kmax=5, dtype="c64")
+    w, offs, R, C, mats = p.program()
+    assert sum(1 for o in offs if int(w[o + 3]) & 4) == p.stats()["blocks"] > 0
+    st.apply_plan(p)
+    got = st.numpy().astype(np.complex128)
+    d2 = float(np.linalg.norm(got - sim.run(c)))
+    rig, typ = bound_for(p)
+    say("||d||2 = %.3e  bound %.3e (typical %.3e)" % (d2, rig, typ))
+    assert d2 <= rig
+
+
 def test_c64_u3_cx_20q_vs_oracle(torch):
     """The 32-qubit U3 + CX recipe at 20 qubits, full depth 60."""
     c = I.random_u3_2q(n=20, depth=60, seed=20003, two="CX")

@@ -363,6 +363,12 @@ def test_replay_u3_cz_and_layered():
         halves += sum(1 for o in offs if int(w[o + 3]) & 4)
         assert np.max(np.abs(replay_plan(p, c.n) - sim.run(c))) <= 1e-12
     assert halves > 0
+    # complex64 (8-byte amplitudes: the split bit sits one position lower in the byte address)
+    c = I.random_u3_2q(n=15, depth=10, seed=15)
+    p = qs.Plan(c, kmax=5, dtype="c64")
+    w, offs, R, C, mats = p.program()
+    assert sum(1 for o in offs if int(w[o + 3]) & 4) > 0
+    assert np.max(np.abs(replay_plan(p, c.n) - sim.run(c))) <= 1e-6
 
 
 def test_replay_swap_plan_is_bit_permutation():
