@@ -412,13 +412,16 @@ __device__ __forceinline__ uint64_t chunk_base(uint64_t c, uint64_t cmask, int n
 // workgroups share a CU, so one's HBM traffic overlaps another's arithmetic.
 // Workgroup size limit: 512 threads when each holds at most 8 amplitudes.
 template <int R> struct MaxThreads { static constexpr int value = (R <= 3) ? 512 : 256; };
-// Two waves per SIMD (two 256-thread workgroups per CU, at most 256 registers
-// per lane) wherever 2^R amplitudes take at most 64 registers; 32 complex128
-// amplitudes (128 registers) get the whole register file instead of spilling.
-template <int R, typename F> struct MinWaves { static constexpr int value = (sizeof(F) * 2 << R) <= 256 ? 2 : 1; };
+// Three waves per SIMD (at most 168 registers per lane) wherever 2^R amplitudes
+// take at most 64 registers, so that three workgroups with half-buffer
+// exchanges share a CU (two for the matrix-core variant, which would spill);
+// 32 complex128 amplitudes (128 registers) get the whole register file.
+template <int R, typename F, bool MF> struct MinWaves {
+    static constexpr int value = (sizeof(F) * 2 << R) <= 256 ? (MF ? 2 : 3) : 1;
+};
 
 template <int R, int KMAX, typename F, bool MF>
-__global__ __launch_bounds__(MaxThreads<R>::value) __attribute__((amdgpu_waves_per_eu(MinWaves<R, F>::value)))
+__global__ __launch_bounds__(MaxThreads<R>::value) __attribute__((amdgpu_waves_per_eu(MinWaves<R, F, MF>::value)))
 void k_block(typename AmpOf<F>::type *__restrict__ amps,
                                               const int *__restrict__ prog, const F *__restrict__ mats, int n)
 {
@@ -660,8 +663,8 @@ hipError_t launch_RK(qs_state *st, const int *d_prog, const F *d_mats, int C, si
 template <int R, typename F>
 hipError_t launch_R(qs_state *st, const int *d_prog, const F *d_mats, int C, size_t tab, int kmax, bool mfma, bool half)
 {
-    // half-buffer exchanges exist only in blocks of rotations and diagonals
-    if (half && (mfma || kmax != 0)) return hipErrorInvalidValue;
+    // half-buffer exchanges exist only outside the matrix-core variant
+    if (half && mfma) return hipErrorInvalidValue;
     if constexpr (R == 5 && std::is_same<F, float>::value) {
         if (mfma) return launch_RK<5, 3, float, true>(st, d_prog, d_mats, C, tab, false);
     }

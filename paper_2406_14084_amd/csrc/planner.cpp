@@ -1277,8 +1277,8 @@ static void check_program(const Plan &p)
         // the dense width compiled into the variant the launcher picks
         const int kw = bm ? 3 : bk == 0 ? 0 : (bk <= 2 || r <= 2) ? std::min(r, 2) : (bk == 3 || r == 3) ? 3 : r;
         const int32_t *ph = w + PROG_HDR + 2 * C;
-        if ((w[3] & 4) && !(kw == 0 && !bm))
-            throw std::logic_error("half-buffer exchanges in a block with dense ops");
+        if ((w[3] & 4) && bm)
+            throw std::logic_error("half-buffer exchanges in a matrix-core block");
         for (int q = 0; q < w[0]; ++q) {
             if (kw == 0 && !bm && (ph[0] & 1))
                 throw std::logic_error("odd op count in a phase of a block without dense ops");
@@ -1336,7 +1336,7 @@ void encode_plan(Plan *p)
         // flags: bit 0 = swap pass; bit 1 = the write-back moves amplitudes between
         // threads' load positions (P_out != P_in), so loads must all complete
         // before any store even when no exchange separates them
-        // Half-buffer exchanges (blocks of the variant without dense ops): when every
+        // Half-buffer exchanges (every block but the complex64 matrix-core ones): when every
         // exchange of the block has a chunk bit b >= 4 at the same thread position j
         // in both layouts, each thread's amplitudes all share b's value before and
         // after, so the exchange runs in two rounds through a buffer of half the
@@ -1346,7 +1346,7 @@ void encode_plan(Plan *p)
         // replaced.)  Less LDS per workgroup, more workgroups per CU.  Wave-index
         // positions are preferred (whole waves take part in a round, no divergence).
         std::vector<int> split_w(blk.phases.size(), -1), split_r(blk.phases.size(), -1), split_b(blk.phases.size(), -1);
-        bool half = bk == 0 && !bm && !blk.permute_only && blk.phases.size() >= 2;
+        bool half = !bm && !blk.permute_only && blk.phases.size() >= 2;
         for (size_t ph = 1; half && ph < blk.phases.size(); ++ph) {
             const Layout &a = blk.phases[ph - 1].lay, &b2 = blk.phases[ph].lay;
             int best = -1;
