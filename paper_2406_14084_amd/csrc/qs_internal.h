@@ -110,13 +110,17 @@ qs_status build_plan_search(const qs_circuit *c, int kmax, const qs_plan_opts *o
 
 // ---------------------------------------------------------------------------
 // Program encoding read by the blocked kernel (int32 words per block):
-//   [0] nphases, [1] C, [2] r, [3] flags (bit 0 swap pass, bit 1 P_out != P_in)
+//   [0] nphases, [1] C, [2] r, [3] flags (bit 0 swap pass, bit 1 P_out != P_in,
+//       bit 2 every exchange runs in two rounds through half the LDS buffer)
 //   [4] table offset (words from block start, multiple of 4), [5] table words, [6..8) 0
 //   [8 .. 8+C)        P_in
 //   [8+C .. 8+2C)     P_out
 //   then per phase:
 //     [0] nops, [1] swz_lo (F nibbles for high bits 0..7), [2] swz_hi (8..15),
-//     [3] 1 + word offset in the LDS table of a copy of the 2 tb thread-bit words below, or 0
+//     [3] bits 0-23: 1 + word offset in the LDS table of a copy of the 2 tb thread-bit words
+//         below, or 0; bits 24-27 / 28-31: 1 + thread position of the split bit in the write /
+//         read layout (equal; 0 = one round through the whole buffer); the split bit is then
+//         dropped from every offset of the exchange block
 //     [4 .. 4+r)      R
 //     [4+r .. 4+C)    T
 //     exchange into this phase (zeros for phase 0), LDS byte offsets:
@@ -135,6 +139,9 @@ qs_status build_plan_search(const qs_circuit *c, int kmax, const qs_plan_opts *o
 //                 matrix in matrix-core operand order (complex64 only)
 //       SIGN_REG: w3 = mask over registers (bit m set: negate register m)
 //       SIGN_ROW: w1 = tmask; w3 = word offset in the table of 2^kt row masks
+//       ROT     : variant = register mask; w1,w2 = offset of (a, b) per set bit, ascending
+//       (blocks without dense ops hold an even op count per phase; a SIGN_REG with k = 0 and
+//       an empty mask pads)
 // The table (per-lane data of diagonal ops) is copied into LDS, after the
 // exchange buffer, once per workgroup.
 // The swizzle for the exchange INTO a phase: slot(l) = l ^ F(l >> 4) where
