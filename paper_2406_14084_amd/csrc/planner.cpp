@@ -1067,8 +1067,45 @@ qs_status build_plan(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan 
             } else if (blk.phases.size() == 1) {
                 lastp.lay = make_layout(Rl, C, r, &store_order);
             } else {
-                lastp.lay = make_layout_keep(Rl, C, r, blk.phases[blk.phases.size() - 2].lay, low_out);
-                // ops of the last phase index registers by R, which is unchanged
+                // the last phase takes the store layout (its ops index registers by R, which
+                // is unchanged) -- unless that leaves its exchange without a split bit while
+                // every earlier exchange has one: then a separate store phase (one more
+                // exchange) keeps the whole block on half-buffer exchanges
+                auto has_split = [&](const Layout &x, const Layout &y) {
+                    for (int j = 0; j < C - r; ++j)
+                        if (x.T[j] == y.T[j] && x.T[j] >= 4) return true;
+                    return false;
+                };
+                const size_t np = blk.phases.size();
+                const Layout relaid = make_layout_keep(Rl, C, r, blk.phases[np - 2].lay, low_out);
+                bool earlier = true;
+                for (size_t q = 1; q + 1 < np; ++q) earlier &= has_split(blk.phases[q - 1].lay, blk.phases[q].lay);
+                earlier &= has_split(blk.phases[np - 2].lay, lastp.lay);
+                bool matrix_cores = false;
+                for (const Phase &P : blk.phases)
+                    for (const Op &op : P.ops) matrix_cores |= p->mfma && op.kind == OP_DENSE && op.k >= 4;
+                if (has_split(blk.phases[np - 2].lay, relaid) || !earlier || matrix_cores) {
+                    lastp.lay = relaid;
+                } else {
+                    int anchor = -1;
+                    for (int j = C - r - 1; j >= L && anchor < 0; --j) {
+                        const int b = lastp.lay.T[j];
+                        if (b >= 4 && !(lowmask_out >> b & 1)) anchor = b;
+                    }
+                    uint32_t R = 0;
+                    int cnt = 0;
+                    for (int i = C - 1; i >= 0 && cnt < r; --i) {
+                        int b = store_order[i];
+                        if (!(lowmask_out >> b & 1) && b != anchor) { R |= 1u << b; ++cnt; }
+                    }
+                    for (int i = C - 1; i >= 0 && cnt < r; --i) {
+                        int b = store_order[i];
+                        if (!(lowmask_out >> b & 1) && !(R >> b & 1)) { R |= 1u << b; ++cnt; }
+                    }
+                    Phase sp;
+                    sp.lay = make_layout_keep(R, C, r, lastp.lay, low_out);
+                    blk.phases.push_back(sp);
+                }
             }
         }
         p->blocks.push_back(std::move(blk));
