@@ -134,8 +134,20 @@ QS_API qs_status qs_create(int n, qs_dtype dtype, qs_state **out);
 
 /* Bind caller-owned device memory of exactly 2^n amplitudes (bytes =
  * 2^n * 16 or 2^n * 8, 256-byte aligned) and a hipStream_t (NULL = default
- * stream) to the handle.  The memory stays the caller's. */
-QS_API qs_status qs_attach(qs_state *st, void *amps_dev, size_t bytes, void *hip_stream);
+ * stream) to the handle.  The memory stays the caller's.
+ * workspace / ws_bytes: caller-owned device scratch on the same device, at
+ * least qs_workspace_size() bytes, 256-byte aligned; the library keeps gate
+ * matrices of 4-5 qubits, swap programs and reduction partials there, in
+ * stream order, and never frees it.  workspace = NULL makes the handle
+ * allocate its own scratch of that size (freed by qs_destroy).
+ * QS_EINVAL for a size or alignment mismatch or a pointer that is not
+ * device memory. */
+QS_API qs_status qs_attach(qs_state *st, void *amps_dev, size_t bytes, void *hip_stream, void *workspace,
+                           size_t ws_bytes);
+
+/* Bytes of device workspace a handle for (n, dtype) needs (qs_attach).
+ * Host only. */
+QS_API qs_status qs_workspace_size(int n, qs_dtype dtype, size_t *bytes);
 
 /* Free the handle (not the attached memory). */
 QS_API qs_status qs_destroy(qs_state *st);
@@ -170,15 +182,19 @@ QS_API qs_status qs_fuse(const qs_circuit *circ, int kmax, const qs_plan_opts *o
 
 /* Run a plan on a state (Alg. 3): for each step, one blocked pass or one
  * swap pass over HBM.  The state is left in canonical qubit order.  The
- * first call uploads the plan's tables to the device (synchronously).
- * Async afterwards. */
-QS_API qs_status qs_apply_plan(qs_state *st, const qs_plan *plan);
+ * plan keeps its device tables (program words, matrices) per device: the
+ * first call on a device allocates them and uploads them with
+ * hipMemcpyAsync on the state's stream (later calls from other streams wait
+ * for that upload through an event); the upload is guarded by a per-plan
+ * lock, so one plan may be applied from several threads.  The plan must
+ * outlive the queued work that uses it.  Async. */
+QS_API qs_status qs_apply_plan(qs_state *st, qs_plan *plan);
 
 /* Same as qs_apply_plan, but records a hipEvent on the bound stream before
  * and after every step and returns each step's device time in ms (ms_out:
  * host array of at least the plan's step count).  *kinds_out (optional)
  * gets 1 for a gate block, 0 for a swap pass.  Synchronises the stream. */
-QS_API qs_status qs_apply_plan_timed(qs_state *st, const qs_plan *plan, float *ms_out, int *kinds_out, int cap);
+QS_API qs_status qs_apply_plan_timed(qs_state *st, qs_plan *plan, float *ms_out, int *kinds_out, int cap);
 
 /* Release a plan and its device tables. */
 QS_API qs_status qs_plan_free(qs_plan *plan);
@@ -219,12 +235,25 @@ QS_API qs_status qs_plan_program(const qs_plan *plan, int32_t *words, size_t cap
 /* ---- readout ------------------------------------------------------------- */
 
 /* p_i = |a_i|^2 for all i, FP64, into caller device memory out_dev (2^n
- * doubles).  Paper: Eq. 1.  Async. */
+ * doubles).  Paper: Sec. II-A Eq. 1 (the squared magnitude of amplitude
+ * a_i is the probability of basis state i).  Async. */
 QS_API qs_status qs_probs(qs_state *st, double *out_dev);
 
 /* sum_t coeff_t <psi|P_t|psi> over nterms Pauli strings (FP64 accumulation),
- * written to *out_host.  Synchronises the stream. */
+ * written to *out_host.  Paper: Sec. II-A Eq. 1 (a measurement outcome i has
+ * probability |a_i|^2; a Pauli string is diagonal, up to the bit flips of
+ * its X/Y letters, in that basis: <P> = sum_i conj(a_{i^x}) ph(i) a_i with
+ * ph(i) = i^{#Y} (-1)^{popcount(i & zmask)}).  Uses the workspace for the
+ * terms and per-workgroup partial sums; the partials are added on the host
+ * in a fixed order.  Synchronises the stream. */
 QS_API qs_status qs_expect(qs_state *st, int nterms, const qs_pauli *terms, double *out_host);
+
+/* Copy amplitudes [first, first + count) of the state (2^n of them,
+ * interleaved re/im at the state's precision, 16 or 8 bytes each) to host
+ * memory host_out, in canonical qubit order.  Paper: Alg. 3's output, the
+ * simulated amplitudes of the state vector.  QS_EINVAL when the range
+ * leaves the state.  Synchronises the stream. */
+QS_API qs_status qs_get_amplitudes(qs_state *st, uint64_t first, uint64_t count, void *host_out);
 
 /* ---- batched QAOA (many small uneven circuits in one launch) ------------- */
 
@@ -245,16 +274,25 @@ typedef struct qs_batch qs_batch;
 
 /* Pack count instances into device tables and a task queue.  An instance of
  * at most 13 qubits (complex64; 12 for complex128) runs whole in one
- * workgroup's LDS; a larger one keeps its state in a workspace and is split
- * into chunk tasks, two passes per layer.  dtype: QS_C64 (complex64 state,
- * FP64 reductions) or QS_C128.  hip_stream: stream for all work.  Allocates
- * device memory for the tables, queue and workspace, owned by the batch.
+ * workgroup's LDS; a larger one keeps its state (and one byte per amplitude
+ * of cached cut values) in a workspace and is split into chunk tasks, two
+ * passes per layer.  dtype: QS_C64 (complex64 state, FP64 reductions) or
+ * QS_C128.  hip_stream: stream for all work.  workspace / ws_bytes:
+ * caller-owned device memory of at least qs_batch_qaoa_workspace_size()
+ * bytes (256-byte aligned) for those states, or NULL to let the batch
+ * allocate it.  The small tables (descriptors, tasks, edges, phases,
+ * counters) are allocated by the batch and freed by qs_batch_free.
  * Launch shape defaults to 256 threads, 2 workgroups per CU and 8 chunks per
- * task until
- * qs_batch_autotune picks one.  Paper: QAOA is one of the benchmark
- * circuits of Sec. VI-A (Table II); batching is this library's addition. */
+ * task until qs_batch_autotune picks one.  Paper: QAOA is one of the
+ * benchmark circuits of Sec. VI-A (Table II); batching is this library's
+ * addition. */
 QS_API qs_status qs_batch_qaoa_create(int count, const qs_qaoa_instance *inst, qs_dtype dtype,
-                               void *hip_stream, qs_batch **out);
+                               void *hip_stream, void *workspace, size_t ws_bytes, qs_batch **out);
+
+/* Workspace bytes qs_batch_qaoa_create needs for these instances (0 when
+ * every instance fits one workgroup's LDS).  Host only. */
+QS_API qs_status qs_batch_qaoa_workspace_size(int count, const qs_qaoa_instance *inst, qs_dtype dtype,
+                                              size_t *bytes);
 
 /* Run every instance in one persistent launch; out_dev: count doubles of
  * <C> in device memory (caller-owned).  use_graph = 1 replays a captured

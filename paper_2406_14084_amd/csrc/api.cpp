@@ -65,7 +65,29 @@ qs_status qs_create(int n, qs_dtype dtype, qs_state **out)
     return QS_OK;
 }
 
-qs_status qs_attach(qs_state *st, void *amps_dev, size_t bytes, void *hip_stream)
+static bool is_device_memory(const void *p, int *device)
+{
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess || attr.type != hipMemoryTypeDevice) {
+        (void)hipGetLastError();
+        return false;
+    }
+    *device = attr.device;
+    return true;
+}
+
+qs_status qs_workspace_size(int n, qs_dtype dtype, size_t *bytes)
+{
+    if (!bytes || n < 1 || n > 34 || (dtype != QS_C128 && dtype != QS_C64)) {
+        set_error("qs_workspace_size: bad arguments");
+        return QS_EINVAL;
+    }
+    *bytes = kScratchBytes;
+    return QS_OK;
+}
+
+qs_status qs_attach(qs_state *st, void *amps_dev, size_t bytes, void *hip_stream, void *workspace, size_t ws_bytes)
 {
     if (!st || !amps_dev) { set_error("qs_attach: null handle or memory"); return QS_EINVAL; }
     const size_t want = ((size_t)1 << st->n) * (st->dtype == QS_C64 ? 8 : 16);
@@ -74,21 +96,40 @@ qs_status qs_attach(qs_state *st, void *amps_dev, size_t bytes, void *hip_stream
         return QS_EINVAL;
     }
     if (((uintptr_t)amps_dev & 255) != 0) { set_error("qs_attach: state memory must be 256-byte aligned"); return QS_EINVAL; }
-    hipPointerAttribute_t attr;
-    hipError_t e = hipPointerGetAttributes(&attr, amps_dev);
-    if (e != hipSuccess || attr.type != hipMemoryTypeDevice) {
-        (void)hipGetLastError();
-        set_error("qs_attach: pointer is not device memory");
-        return QS_EINVAL;
+    int device = -1;
+    if (!is_device_memory(amps_dev, &device)) { set_error("qs_attach: pointer is not device memory"); return QS_EINVAL; }
+    if (workspace) {
+        int wdev = -1;
+        if (ws_bytes < kScratchBytes) {
+            set_error("qs_attach: workspace needs " + std::to_string(kScratchBytes) + " bytes, got " + std::to_string(ws_bytes));
+            return QS_EINVAL;
+        }
+        if (((uintptr_t)workspace & 255) != 0) { set_error("qs_attach: workspace must be 256-byte aligned"); return QS_EINVAL; }
+        if (!is_device_memory(workspace, &wdev) || wdev != device) {
+            set_error("qs_attach: workspace is not device memory on the state's device");
+            return QS_EINVAL;
+        }
     }
-    QS_CHECK_HIP(hipSetDevice(attr.device), "qs_attach: hipSetDevice");
-    if (!st->d_scratch || st->device != attr.device) {
-        if (st->d_scratch) (void)hipFree(st->d_scratch);
+    QS_CHECK_HIP(hipSetDevice(device), "qs_attach: hipSetDevice");
+    if (workspace) {
+        if (st->own_scratch && st->d_scratch) {
+            (void)hipSetDevice(st->device);
+            (void)hipStreamSynchronize(st->stream);
+            (void)hipFree(st->d_scratch);
+            QS_CHECK_HIP(hipSetDevice(device), "qs_attach: hipSetDevice");
+        }
+        st->d_scratch = workspace;
+        st->scratch_bytes = ws_bytes;
+        st->own_scratch = false;
+    } else if (!st->own_scratch || !st->d_scratch || st->device != device) {
+        if (st->own_scratch && st->d_scratch) (void)hipFree(st->d_scratch);
         st->d_scratch = nullptr;
+        st->own_scratch = false;
         QS_CHECK_HIP(hipMalloc(&st->d_scratch, kScratchBytes), "qs_attach: hipMalloc scratch");
         st->scratch_bytes = kScratchBytes;
+        st->own_scratch = true;
     }
-    st->device = attr.device;
+    st->device = device;
     st->amps = amps_dev;
     st->bytes = bytes;
     st->stream = reinterpret_cast<hipStream_t>(hip_stream);
@@ -98,12 +139,29 @@ qs_status qs_attach(qs_state *st, void *amps_dev, size_t bytes, void *hip_stream
 qs_status qs_destroy(qs_state *st)
 {
     if (!st) return QS_OK;
-    if (st->d_scratch) {
+    if (st->own_scratch && st->d_scratch) {
         (void)hipSetDevice(st->device);
         (void)hipStreamSynchronize(st->stream);
         (void)hipFree(st->d_scratch);
     }
     delete st;
+    return QS_OK;
+}
+
+qs_status qs_get_amplitudes(qs_state *st, uint64_t first, uint64_t count, void *host_out)
+{
+    qs_status s = check_attached(st, "qs_get_amplitudes");
+    if (s) return s;
+    const uint64_t N = 1ull << st->n;
+    if ((count && !host_out) || first > N || count > N - first) {
+        set_error("qs_get_amplitudes: range outside the state or null output");
+        return QS_EINVAL;
+    }
+    if (!count) return QS_OK;
+    const size_t ab = st->dtype == QS_C64 ? 8 : 16;
+    QS_CHECK_HIP(hipMemcpyAsync(host_out, reinterpret_cast<const char *>(st->amps) + first * ab, count * ab,
+                                hipMemcpyDeviceToHost, st->stream), "qs_get_amplitudes: copy");
+    QS_CHECK_HIP(hipStreamSynchronize(st->stream), "qs_get_amplitudes: sync");
     return QS_OK;
 }
 
@@ -208,58 +266,95 @@ qs_status qs_fuse(const qs_circuit *circ, int kmax, const qs_plan_opts *opts, qs
     return QS_OK;
 }
 
-static qs_status upload_plan(qs_plan *pl, int device)
+// Device tables of a plan on the state's device: allocated and uploaded with
+// hipMemcpyAsync on the state's stream the first time, under the plan's lock;
+// a later user on another stream waits for the upload through its event.
+static qs_status plan_tables(qs_state *st, qs_plan *pl, const void **d_prog, const void **d_mats, const char *fn)
 {
-    qs::Plan &p = pl->p;
-    if (p.uploaded && p.upload_device == device) return QS_OK;
-    if (p.d_prog) { (void)hipFree(p.d_prog); p.d_prog = nullptr; }
-    if (p.d_mats) { (void)hipFree(p.d_mats); p.d_mats = nullptr; }
-    const size_t pb = p.h_prog.size() * sizeof(int32_t);
+    const qs::Plan &p = pl->p;
+    std::lock_guard<std::mutex> g(pl->mu);
+    for (const qs_plan::DevTables &t : pl->dev) {
+        if (t.device != st->device) continue;
+        if (t.stream != st->stream) QS_CHECK_HIP(hipStreamWaitEvent(st->stream, t.ready, 0), fn);
+        *d_prog = t.d_prog;
+        *d_mats = t.d_mats;
+        return QS_OK;
+    }
+    qs_plan::DevTables t;
+    t.device = st->device;
+    t.stream = st->stream;
+    const size_t pb = std::max<size_t>(4, p.h_prog.size() * sizeof(int32_t));
     const size_t mb = (p.dtype == QS_C64) ? p.h_mats32.size() * sizeof(float) : p.h_mats.size() * sizeof(double);
-    QS_CHECK_HIP(hipMalloc(&p.d_prog, pb), "qs_apply_plan: hipMalloc program");
-    QS_CHECK_HIP(hipMalloc(&p.d_mats, mb), "qs_apply_plan: hipMalloc matrices");
-    QS_CHECK_HIP(hipMemcpy(p.d_prog, p.h_prog.data(), pb, hipMemcpyHostToDevice), "qs_apply_plan: upload program");
+    hipError_t e = hipMalloc(&t.d_prog, pb);
+    if (e == hipSuccess) e = hipMalloc(&t.d_mats, std::max<size_t>(mb, 16));
+    if (e == hipSuccess && !p.h_prog.empty())
+        e = hipMemcpyAsync(t.d_prog, p.h_prog.data(), p.h_prog.size() * sizeof(int32_t), hipMemcpyHostToDevice, st->stream);
     const void *src = (p.dtype == QS_C64) ? (const void *)p.h_mats32.data() : (const void *)p.h_mats.data();
-    QS_CHECK_HIP(hipMemcpy(p.d_mats, src, mb, hipMemcpyHostToDevice), "qs_apply_plan: upload matrices");
-    p.uploaded = true;
-    p.upload_device = device;
+    if (e == hipSuccess && mb) e = hipMemcpyAsync(t.d_mats, src, mb, hipMemcpyHostToDevice, st->stream);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&t.ready, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(t.ready, st->stream);
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(st->stream);
+        if (t.d_prog) (void)hipFree(t.d_prog);
+        if (t.d_mats) (void)hipFree(t.d_mats);
+        if (t.ready) (void)hipEventDestroy(t.ready);
+        return hip_fail(e, fn);
+    }
+    pl->dev.push_back(t);
+    *d_prog = t.d_prog;
+    *d_mats = t.d_mats;
     return QS_OK;
 }
 
-qs_status qs_apply_plan(qs_state *st, const qs_plan *plan)
+static qs_status check_plan(qs_state *st, const qs_plan *plan, const char *fn)
 {
-    qs_status rc = check_attached(st, "qs_apply_plan");
-    if (rc) return rc;
-    if (!plan) { set_error("qs_apply_plan: null plan"); return QS_EINVAL; }
+    if (!plan) { set_error(std::string(fn) + ": null plan"); return QS_EINVAL; }
     const qs::Plan &p = plan->p;
     if (p.n != st->n || p.dtype != st->dtype) {
-        set_error("qs_apply_plan: plan is for n=" + std::to_string(p.n) + " dtype " + std::to_string((int)p.dtype) +
+        set_error(std::string(fn) + ": plan is for n=" + std::to_string(p.n) + " dtype " + std::to_string((int)p.dtype) +
                   ", state is n=" + std::to_string(st->n) + " dtype " + std::to_string((int)st->dtype));
         return QS_ESTATE;
     }
-    if (p.n - p.C > 31) { set_error("qs_apply_plan: too many chunks for one launch"); return QS_EUNSUPPORTED; }
-    rc = upload_plan(const_cast<qs_plan *>(plan), st->device);
-    if (rc) return rc;
-    return run_blocks(st, p, reinterpret_cast<const int *>(p.d_prog), p.d_mats, "qs_apply_plan: launch");
+    if (!p.blocks.empty() && p.n - p.C > 31) {
+        set_error(std::string(fn) + ": too many chunks for one launch");
+        return QS_EUNSUPPORTED;
+    }
+    return QS_OK;
 }
 
-qs_status qs_apply_plan_timed(qs_state *st, const qs_plan *plan, float *ms_out, int *kinds_out, int cap)
+qs_status qs_apply_plan(qs_state *st, qs_plan *plan)
+{
+    qs_status rc = check_attached(st, "qs_apply_plan");
+    if (rc) return rc;
+    rc = check_plan(st, plan, "qs_apply_plan");
+    if (rc) return rc;
+    const void *d_prog = nullptr, *d_mats = nullptr;
+    rc = plan_tables(st, plan, &d_prog, &d_mats, "qs_apply_plan: upload");
+    if (rc) return rc;
+    return run_blocks(st, plan->p, reinterpret_cast<const int *>(d_prog), d_mats, "qs_apply_plan: launch");
+}
+
+qs_status qs_apply_plan_timed(qs_state *st, qs_plan *plan, float *ms_out, int *kinds_out, int cap)
 {
     qs_status rc = check_attached(st, "qs_apply_plan_timed");
     if (rc) return rc;
-    if (!plan || !ms_out) { set_error("qs_apply_plan_timed: null argument"); return QS_EINVAL; }
+    if (!ms_out) { set_error("qs_apply_plan_timed: null argument"); return QS_EINVAL; }
+    rc = check_plan(st, plan, "qs_apply_plan_timed");
+    if (rc) return rc;
     const qs::Plan &p = plan->p;
-    if (p.n != st->n || p.dtype != st->dtype) { set_error("qs_apply_plan_timed: plan/state mismatch"); return QS_ESTATE; }
     const int ns = (int)p.blocks.size();
     if (cap < ns) { set_error("qs_apply_plan_timed: output too small"); return QS_EINVAL; }
-    rc = upload_plan(const_cast<qs_plan *>(plan), st->device);
+    const void *d_prog = nullptr, *d_mats = nullptr;
+    rc = plan_tables(st, plan, &d_prog, &d_mats, "qs_apply_plan_timed: upload");
     if (rc) return rc;
-    std::vector<hipEvent_t> ev(ns + 1);
-    for (auto &e : ev) QS_CHECK_HIP(hipEventCreate(&e), "qs_apply_plan_timed: event");
+    std::vector<hipEvent_t> ev(ns + 1, nullptr);
     qs_status out = QS_OK;
-    hipError_t e = hipEventRecord(ev[0], st->stream);
+    hipError_t e = hipSuccess;
+    for (auto &x : ev)
+        if (e == hipSuccess) e = hipEventCreate(&x);
+    if (e == hipSuccess) e = hipEventRecord(ev[0], st->stream);
     for (int b = 0; b < ns && e == hipSuccess; ++b) {
-        e = qs::launch_block(st, p, b);
+        e = qs::launch_block(st, p, d_prog, d_mats, b);
         if (e == hipSuccess) e = hipEventRecord(ev[b + 1], st->stream);
     }
     if (e == hipSuccess) e = hipEventSynchronize(ev[ns]);
@@ -271,15 +366,26 @@ qs_status qs_apply_plan_timed(qs_state *st, const qs_plan *plan, float *ms_out, 
         ms_out[b] = ms;
         if (kinds_out) kinds_out[b] = p.blocks[b].permute_only ? 0 : 1;
     }
-    for (auto &x : ev) (void)hipEventDestroy(x);
+    for (auto &x : ev)
+        if (x) (void)hipEventDestroy(x);
     return out;
 }
 
 qs_status qs_plan_free(qs_plan *plan)
 {
     if (!plan) return QS_OK;
-    if (plan->p.d_prog) (void)hipFree(plan->p.d_prog);
-    if (plan->p.d_mats) (void)hipFree(plan->p.d_mats);
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    for (qs_plan::DevTables &t : plan->dev) {
+        (void)hipSetDevice(t.device);
+        if (t.ready) {
+            (void)hipEventSynchronize(t.ready);
+            (void)hipEventDestroy(t.ready);
+        }
+        if (t.d_prog) (void)hipFree(t.d_prog);
+        if (t.d_mats) (void)hipFree(t.d_mats);
+    }
+    if (cur >= 0 && !plan->dev.empty()) (void)hipSetDevice(cur);
     delete plan;
     return QS_OK;
 }

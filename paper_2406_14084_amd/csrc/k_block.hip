@@ -20,6 +20,7 @@
 //   - the write-back may permute the chunk's bits (P_out), which performs a
 //     qubit swap at no extra HBM pass.
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "amp.h"
@@ -642,11 +643,19 @@ hipError_t launch_RK(qs_state *st, const int *d_prog, const F *d_mats, int C, si
     const size_t lds = ((size_t)1 << (half ? C - 1 : C)) * sizeof(V) + ((tab_bytes + 15) & ~(size_t)15);
     if (lds > 160u * 1024u) return hipErrorInvalidValue;
     auto kern = k_block<R, KMAX, F, MF>;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    // the LDS limit is raised once per device (devices numbered below 64), under a lock
+    static std::mutex mu;
+    static uint64_t done = 0;
+    {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
         if (e != hipSuccess) return e;
-        attr_set = true;
+        std::lock_guard<std::mutex> g(mu);
+        if (dev >= 64 || !((done >> dev) & 1u)) {
+            e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            if (e != hipSuccess) return e;
+            if (dev < 64) done |= 1ull << dev;
+        }
     }
     const unsigned threads = 1u << (C - R);
     const uint64_t nchunks = 1ull << (st->n - C);
@@ -704,12 +713,12 @@ hipError_t launch_block_prog(qs_state *st, int r, int C, const int *d_prog, cons
                             half);
 }
 
-hipError_t launch_block(qs_state *st, const Plan &p, int b)
+hipError_t launch_block(qs_state *st, const Plan &p, const void *d_prog, const void *d_mats, int b)
 {
-    const int *prog = reinterpret_cast<const int *>(p.d_prog) + p.prog_off[b];
+    const int *prog = reinterpret_cast<const int *>(d_prog) + p.prog_off[b];
     const size_t tab_bytes = (size_t)p.h_prog[p.prog_off[b] + 5] * 4;
     const bool half = (p.h_prog[p.prog_off[b] + 3] & 4) != 0;
-    return launch_block_prog(st, p.r, p.C, prog, p.d_mats, tab_bytes, p.block_kmax[b], p.block_mfma[b] != 0, half);
+    return launch_block_prog(st, p.r, p.C, prog, d_mats, tab_bytes, p.block_kmax[b], p.block_mfma[b] != 0, half);
 }
 
 }  // namespace qs

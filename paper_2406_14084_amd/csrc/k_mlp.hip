@@ -88,6 +88,15 @@ __global__ void k_linear_bwd_w(const float *__restrict__ dout, const float *__re
     }
 }
 
+// a[i] = b[i] = 0 (the Adam moments)
+__global__ void k_zero2(float *__restrict__ a, float *__restrict__ b, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        a[i] = 0.f;
+        b[i] = 0.f;
+    }
+}
+
 // Adam with bias correction; omb1 = 1 - b1 and omb2 = 1 - b2 come from the
 // host in double precision (1 - 0.999f in FP32 is off by 1.3e-5 relative).
 __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m, float *__restrict__ v,
@@ -214,6 +223,11 @@ qs_status qs_costmodel_set_params(qs_costmodel *m, const float *host_in)
 {
     if (!m || !host_in) { set_error("qs_costmodel_set_params: null argument"); return QS_EINVAL; }
     hipError_t e = hipMemcpyAsync(m->params, host_in, NPARAM * sizeof(float), hipMemcpyHostToDevice, m->stream);
+    if (e == hipSuccess) {
+        // a new starting point: Adam starts over (step count and both moments)
+        hipLaunchKernelGGL(k_zero2, dim3((NPARAM + 255) / 256), dim3(256), 0, m->stream, m->m, m->v, (int)NPARAM);
+        e = hipGetLastError();
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
     if (e != hipSuccess) return hip_fail(e, "qs_costmodel_set_params");
     m->t = 0;

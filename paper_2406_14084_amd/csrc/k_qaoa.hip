@@ -316,6 +316,7 @@ struct qs_batch {
     void *d_inst = nullptr, *d_tasks = nullptr, *d_seq_tasks = nullptr, *d_edges = nullptr, *d_tab = nullptr;
     void *d_work = nullptr, *d_ctr = nullptr;
     void *d_czw = nullptr;   // C(z) bytes of the large instances
+    bool own_work = true;    // d_work / d_czw allocated by the batch (no caller workspace)
     int ntasks = 0;
     std::vector<int> seq_begin, seq_count;   // per instance: its tasks in d_seq_tasks
     int nctr = 0;                            // [0] next, [1] err, [2..2+count) done, then one "next" per sequential launch
@@ -379,24 +380,86 @@ hipError_t run_batch(qs_batch *b, double *out, int threads, int grid_per_cu, int
 
 extern "C" {
 
-qs_status qs_batch_qaoa_create(int count, const qs_qaoa_instance *inst, qs_dtype dtype, void *hip_stream,
-                               qs_batch **out)
+}  // extern "C"
+
+namespace {
+
+qs_status check_instances(int count, const qs_qaoa_instance *inst, qs_dtype dtype, const char *fn)
 {
     using namespace qs;
-    if (!out || count < 1 || !inst) { set_error("qs_batch_qaoa_create: bad arguments"); return QS_EINVAL; }
-    if (dtype != QS_C64 && dtype != QS_C128) { set_error("qs_batch_qaoa_create: bad dtype"); return QS_EINVAL; }
+    if (count < 1 || !inst) { set_error(std::string(fn) + ": bad arguments"); return QS_EINVAL; }
+    if (dtype != QS_C64 && dtype != QS_C128) { set_error(std::string(fn) + ": bad dtype"); return QS_EINVAL; }
     const int CB = dtype == QS_C64 ? kCB64 : kCB128;
-    const size_t abytes = dtype == QS_C64 ? 8 : 16;
     for (int i = 0; i < count; ++i) {
         const qs_qaoa_instance &q = inst[i];
         if (q.n < 2 || q.n > 20 || q.nedges < 0 || q.nedges > 64 || q.p < 1 || q.p > 64 || (q.nedges && !q.edges) ||
             !q.gammas || !q.betas) {
-            set_error("qs_batch_qaoa_create: instance " + std::to_string(i) + " out of range (n 2..20, edges <= 64, p 1..64)");
+            set_error(std::string(fn) + ": instance " + std::to_string(i) + " out of range (n 2..20, edges <= 64, p 1..64)");
             return QS_EINVAL;
         }
         for (int e = 0; e < 2 * q.nedges; ++e)
-            if (q.edges[e] < 0 || q.edges[e] >= q.n) { set_error("qs_batch_qaoa_create: bad edge"); return QS_EINVAL; }
-        if (q.n > CB && q.n - CB > CB) { set_error("qs_batch_qaoa_create: instance too large"); return QS_EINVAL; }
+            if (q.edges[e] < 0 || q.edges[e] >= q.n) { set_error(std::string(fn) + ": bad edge"); return QS_EINVAL; }
+        if (q.n > CB && q.n - CB > CB) { set_error(std::string(fn) + ": instance too large"); return QS_EINVAL; }
+    }
+    return QS_OK;
+}
+
+// amplitudes of the instances that keep their state outside LDS
+long long work_amplitudes(int count, const qs_qaoa_instance *inst, qs_dtype dtype)
+{
+    const int CB = dtype == QS_C64 ? kCB64 : kCB128;
+    long long work = 0;
+    for (int i = 0; i < count; ++i)
+        if (inst[i].n > CB) work += 1ll << inst[i].n;
+    return work;
+}
+
+// workspace layout: states (work amplitudes), then one cut-value byte per amplitude
+size_t work_bytes(long long work, qs_dtype dtype, size_t *cz_off)
+{
+    const size_t ab = dtype == QS_C64 ? 8 : 16;
+    const size_t states = ((size_t)work * ab + 255) & ~(size_t)255;
+    *cz_off = states;
+    return work ? states + (((size_t)work + 255) & ~(size_t)255) : 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+qs_status qs_batch_qaoa_workspace_size(int count, const qs_qaoa_instance *inst, qs_dtype dtype, size_t *bytes)
+{
+    using namespace qs;
+    if (!bytes) { set_error("qs_batch_qaoa_workspace_size: null output"); return QS_EINVAL; }
+    qs_status rc = check_instances(count, inst, dtype, "qs_batch_qaoa_workspace_size");
+    if (rc) return rc;
+    size_t cz = 0;
+    *bytes = work_bytes(work_amplitudes(count, inst, dtype), dtype, &cz);
+    return QS_OK;
+}
+
+qs_status qs_batch_qaoa_create(int count, const qs_qaoa_instance *inst, qs_dtype dtype, void *hip_stream,
+                               void *workspace, size_t ws_bytes, qs_batch **out)
+{
+    using namespace qs;
+    if (!out) { set_error("qs_batch_qaoa_create: bad arguments"); return QS_EINVAL; }
+    qs_status rc0 = check_instances(count, inst, dtype, "qs_batch_qaoa_create");
+    if (rc0) return rc0;
+    const int CB = dtype == QS_C64 ? kCB64 : kCB128;
+    const size_t abytes = dtype == QS_C64 ? 8 : 16;
+    size_t cz_off = 0;
+    const size_t need = work_bytes(work_amplitudes(count, inst, dtype), dtype, &cz_off);
+    if (workspace) {
+        hipPointerAttribute_t attr;
+        int cur = -1;
+        (void)hipGetDevice(&cur);
+        if (ws_bytes < need || ((uintptr_t)workspace & 255) != 0 || hipPointerGetAttributes(&attr, workspace) != hipSuccess ||
+            attr.type != hipMemoryTypeDevice || attr.device != cur) {
+            (void)hipGetLastError();
+            set_error("qs_batch_qaoa_create: workspace must be 256-byte aligned device memory of the current device, at "
+                      "least " + std::to_string(need) + " bytes");
+            return QS_EINVAL;
+        }
     }
     qs_batch *b = new qs_batch();
     b->count = count;
@@ -494,8 +557,14 @@ qs_status qs_batch_qaoa_create(int count, const qs_qaoa_instance *inst, qs_dtype
     } else {
         alloc(&b->d_tab, tab.size() * sizeof(double), tab.data(), "qs_batch_qaoa_create: tables");
     }
-    alloc(&b->d_work, (size_t)work * abytes, nullptr, "qs_batch_qaoa_create: workspace");
-    alloc(&b->d_czw, (size_t)std::max<long long>(work, 1), nullptr, "qs_batch_qaoa_create: cut workspace");
+    if (workspace) {
+        b->own_work = false;
+        b->d_work = need ? workspace : nullptr;
+        b->d_czw = need ? reinterpret_cast<char *>(workspace) + cz_off : nullptr;
+    } else {
+        alloc(&b->d_work, (size_t)work * abytes, nullptr, "qs_batch_qaoa_create: workspace");
+        alloc(&b->d_czw, (size_t)std::max<long long>(work, 1), nullptr, "qs_batch_qaoa_create: cut workspace");
+    }
     alloc(&b->d_ctr, (size_t)b->nctr * sizeof(unsigned), nullptr, "qs_batch_qaoa_create: counters");
     if (rc) {
         qs_batch_free(b);
@@ -622,8 +691,11 @@ qs_status qs_batch_free(qs_batch *b)
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
     if (b->gstream) (void)hipStreamDestroy(b->gstream);
-    for (void *p : {b->d_inst, b->d_tasks, b->d_seq_tasks, b->d_edges, b->d_tab, b->d_work, b->d_ctr, b->d_czw})
+    for (void *p : {b->d_inst, b->d_tasks, b->d_seq_tasks, b->d_edges, b->d_tab, b->d_ctr})
         if (p) (void)hipFree(p);
+    if (b->own_work)
+        for (void *p : {b->d_work, b->d_czw})
+            if (p) (void)hipFree(p);
     delete b;
     return QS_OK;
 }

@@ -305,7 +305,12 @@ qs_status build_plan_search(const qs_circuit *c, int kmax, const qs_plan_opts *o
     }
     std::string perr;
     rc = predict_plans(o->cost_model, keep, &perr);
-    if (rc == QS_OK && std::isfinite(heur.pred_ms)) {
+    if (rc != QS_OK) {
+        // no silent fallback: the caller asked for the learned planner
+        *err = "qs_fuse: cost-model prediction failed: " + perr;
+        return rc;
+    }
+    if (std::isfinite(heur.pred_ms)) {
         for (Candidate *cd : keep)
             if (std::isfinite(cd->pred_ms) && cd->pred_ms < best->pred_ms) best = cd;
         // fallback: a candidate replaces the heuristic only for a predicted gain of at least 2 %

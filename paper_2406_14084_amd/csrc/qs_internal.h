@@ -5,6 +5,7 @@
 
 #include <complex>
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -81,12 +82,7 @@ struct Plan {
     qs_plan_stats stats{};
     std::string error;
 
-    // device tables (uploaded on first use)
-    bool uploaded = false;
-    int upload_device = -1;
-    void *d_prog = nullptr;             // int32 program words for all blocks
-    void *d_mats = nullptr;             // matrices (FP64 or FP32 by dtype)
-    std::vector<int64_t> prog_off;      // per block: offset of its program in d_prog (int32 words)
+    std::vector<int64_t> prog_off;      // per block: offset of its program in the program words (int32 words)
     std::vector<int> block_kmax;        // per block: widest vector dense op (selects the kernel variant)
     std::vector<char> block_mfma;       // per block: has matrix-core ops (complex64 variant with them)
     std::vector<int32_t> h_prog;
@@ -163,10 +159,22 @@ struct qs_state {
     int device = -1;
     void *d_scratch = nullptr;     // small device scratch: gate matrices for k >= 4, reduction partials
     size_t scratch_bytes = 0;
+    bool own_scratch = false;      // allocated by qs_attach (no caller workspace): freed by qs_destroy
 };
 
+// A plan and its device tables, one set per device it has run on (uploaded
+// on first use there, under the lock).
 struct qs_plan {
+    struct DevTables {
+        int device = -1;
+        void *d_prog = nullptr;        // int32 program words of all steps
+        void *d_mats = nullptr;        // matrices (FP64 or FP32 by dtype)
+        hipEvent_t ready = nullptr;    // recorded after the upload on the uploading stream
+        hipStream_t stream = nullptr;  // that stream
+    };
     qs::Plan p;
+    std::mutex mu;
+    std::vector<DevTables> dev;
 };
 
 // error helpers (api.cpp)
@@ -183,7 +191,7 @@ hipError_t launch_swap(qs_state *st, int s, const int *a, const int *b);
 hipError_t launch_probs(qs_state *st, double *out);
 hipError_t launch_expect(qs_state *st, int nterms, const qs_pauli *terms, double *partials, int nparts);
 int expect_partials(int n);
-hipError_t launch_block(qs_state *st, const Plan &p, int b);
+hipError_t launch_block(qs_state *st, const Plan &p, const void *d_prog, const void *d_mats, int b);
 hipStream_t costmodel_stream(const qs_costmodel *m);
 int costmodel_device(const qs_costmodel *m);
 hipError_t launch_block_prog(qs_state *st, int r, int C, const int *d_prog, const void *d_mats, size_t tab_bytes,

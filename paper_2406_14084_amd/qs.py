@@ -63,7 +63,9 @@ _lib = None
 _P = C.c_void_p
 SIGNATURES = {
     "qs_create": (C.c_int, [C.c_int, C.c_int, C.POINTER(_P)]),
-    "qs_attach": (C.c_int, [_P, _P, C.c_size_t, _P]),
+    "qs_attach": (C.c_int, [_P, _P, C.c_size_t, _P, _P, C.c_size_t]),
+    "qs_workspace_size": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_size_t)]),
+    "qs_get_amplitudes": (C.c_int, [_P, C.c_uint64, C.c_uint64, _P]),
     "qs_destroy": (C.c_int, [_P]),
     "qs_init_zero": (C.c_int, [_P]),
     "qs_init_basis": (C.c_int, [_P, C.c_uint64]),
@@ -82,7 +84,8 @@ SIGNATURES = {
                                   C.POINTER(C.c_int), C.POINTER(C.c_double), C.c_size_t, C.POINTER(C.c_size_t)]),
     "qs_probs": (C.c_int, [_P, _P]),
     "qs_expect": (C.c_int, [_P, C.c_int, C.POINTER(Pauli_C), C.POINTER(C.c_double)]),
-    "qs_batch_qaoa_create": (C.c_int, [C.c_int, C.POINTER(QaoaInst_C), C.c_int, _P, C.POINTER(_P)]),
+    "qs_batch_qaoa_create": (C.c_int, [C.c_int, C.POINTER(QaoaInst_C), C.c_int, _P, _P, C.c_size_t, C.POINTER(_P)]),
+    "qs_batch_qaoa_workspace_size": (C.c_int, [C.c_int, C.POINTER(QaoaInst_C), C.c_int, C.POINTER(C.c_size_t)]),
     "qs_batch_qaoa_run": (C.c_int, [_P, _P, C.c_int]),
     "qs_batch_qaoa_run_sequential": (C.c_int, [_P, _P]),
     "qs_batch_free": (C.c_int, [_P]),
@@ -145,7 +148,10 @@ class State:
     """An n-qubit state vector in a torch tensor (complex128 or complex64,
     on a GPU) bound to a libqs handle and a stream."""
 
-    def __init__(self, n, dtype="c128", device="cuda", stream=None, tensor=None):
+    def __init__(self, n, dtype="c128", device="cuda", stream=None, tensor=None, workspace=True):
+        """workspace=True: a torch-owned uint8 tensor of qs_workspace_size()
+        bytes is handed to the library as its scratch; False: the handle
+        allocates its own."""
         torch = _torch()
         self.n = int(n)
         self.dtype = QS_C64 if dtype in ("c64", "complex64", QS_C64) else QS_C128
@@ -158,9 +164,16 @@ class State:
         h = C.c_void_p()
         check(lib().qs_create(self.n, self.dtype, C.byref(h)))
         self.h = h
+        self.workspace = None
+        ws_ptr, ws_bytes = None, 0
+        if workspace:
+            nb = C.c_size_t()
+            check(lib().qs_workspace_size(self.n, self.dtype, C.byref(nb)))
+            self.workspace = torch.empty(nb.value, dtype=torch.uint8, device=tensor.device)
+            ws_ptr, ws_bytes = C.c_void_p(self.workspace.data_ptr()), nb.value
         with torch.cuda.device(tensor.device):
             check(lib().qs_attach(h, C.c_void_p(tensor.data_ptr()), tensor.numel() * tensor.element_size(),
-                                  _stream_ptr(stream)))
+                                  _stream_ptr(stream), ws_ptr, ws_bytes))
 
     def close(self):
         if getattr(self, "h", None) is not None and _lib is not None:
@@ -225,6 +238,13 @@ class State:
 
     def numpy(self):
         return self.tensor.cpu().numpy()
+
+    def amplitudes(self, first=0, count=None):
+        """Amplitudes [first, first + count) copied to host through the C ABI."""
+        count = (1 << self.n) - first if count is None else int(count)
+        out = np.empty(count, dtype=np.complex64 if self.dtype == QS_C64 else np.complex128)
+        check(lib().qs_get_amplitudes(self.h, int(first), count, C.c_void_p(out.ctypes.data)))
+        return out
 
 
 class Plan:
@@ -412,8 +432,14 @@ class QaoaBatch:
             self._keep += [e, g, b]
             arr[i] = QaoaInst_C(q.n, len(q.edges), len(g), _ip(e), _dp(g), _dp(b))
         self.dtype = QS_C64 if dtype in ("c64", "complex64", QS_C64) else QS_C128
+        nb = C.c_size_t()
+        check(lib().qs_batch_qaoa_workspace_size(self.count, arr, self.dtype, C.byref(nb)))
+        # the instances' states live in a torch-owned workspace
+        self.workspace = torch.empty(max(nb.value, 256), dtype=torch.uint8, device="cuda")
         h = C.c_void_p()
-        check(lib().qs_batch_qaoa_create(self.count, arr, self.dtype, _stream_ptr(stream), C.byref(h)))
+        check(lib().qs_batch_qaoa_create(self.count, arr, self.dtype, _stream_ptr(stream),
+                                         C.c_void_p(self.workspace.data_ptr()) if nb.value else None, nb.value,
+                                         C.byref(h)))
         self.h = h
         self.out = torch.zeros(self.count, dtype=torch.float64, device="cuda")
 

@@ -64,3 +64,52 @@ def test_null_arguments():
     assert L.qs_init_zero(None) == -1
     assert L.qs_apply_plan(None, None) == -1
     assert L.qs_fuse(None, 3, None, None) == -1
+
+
+def test_workspace_size_query():
+    L = qs.lib()
+    nb = C.c_size_t()
+    assert L.qs_workspace_size(30, 0, C.byref(nb)) == 0 and nb.value >= 1 << 20
+    assert L.qs_workspace_size(0, 0, C.byref(nb)) == -1
+    assert L.qs_workspace_size(10, 5, C.byref(nb)) == -1
+    assert L.qs_workspace_size(10, 0, None) == -1
+
+
+def test_attach_rejects_host_memory_and_bad_workspace():
+    L = qs.lib()
+    h = C.c_void_p()
+    assert L.qs_create(4, 0, C.byref(h)) == 0
+    buf = C.create_string_buffer(16 * 16 + 256)
+    p = (C.addressof(buf) + 255) & ~255
+    # wrong size first (checked before any HIP call), then host memory
+    assert L.qs_attach(h, C.c_void_p(p), 100, None, None, 0) == -1
+    assert "expected 256 bytes" in L.qs_last_error().decode()
+    assert L.qs_attach(h, C.c_void_p(p + 16), 256, None, None, 0) == -1
+    assert "aligned" in L.qs_last_error().decode()
+    assert L.qs_attach(h, C.c_void_p(p), 256, None, None, 0) == -1
+    assert "device memory" in L.qs_last_error().decode()
+    assert L.qs_get_amplitudes(h, 0, 1, C.c_void_p(p)) == -5
+    assert L.qs_destroy(h) == 0
+
+
+def test_batch_workspace_size():
+    """States of instances above the in-LDS limit (13 qubits for complex64)
+    go to the workspace: 2^n amplitudes plus one cut-value byte each."""
+    import numpy as np
+    edges = np.array([0, 1, 1, 2, 2, 0], dtype=np.int32)
+    g = np.array([0.3], dtype=np.float64)
+    b = np.array([0.2], dtype=np.float64)
+    L = qs.lib()
+
+    def inst(n):
+        return qs.QaoaInst_C(n, 3, 1, edges.ctypes.data_as(C.POINTER(C.c_int)),
+                             g.ctypes.data_as(C.POINTER(C.c_double)), b.ctypes.data_as(C.POINTER(C.c_double)))
+    arr = (qs.QaoaInst_C * 3)(inst(10), inst(14), inst(16))
+    nb = C.c_size_t()
+    assert L.qs_batch_qaoa_workspace_size(3, arr, 1, C.byref(nb)) == 0
+    amps = (1 << 14) + (1 << 16)
+    assert nb.value == amps * 8 + amps
+    assert L.qs_batch_qaoa_workspace_size(1, arr, 1, C.byref(nb)) == 0 and nb.value == 0
+    bad = (qs.QaoaInst_C * 1)(inst(21))
+    assert L.qs_batch_qaoa_workspace_size(1, bad, 1, C.byref(nb)) == -1
+    assert L.qs_batch_qaoa_create(1, bad, 1, None, None, 0, None) == -1

@@ -1,27 +1,9 @@
 """complex64 path: FP32 state, matrices composed in FP64 and rounded once,
-FP64 readouts.  Parity is stated as a rigorous first-order error bound.
-
-Bound (standard floating-point model, unit roundoff u = 2^-24, gamma_m = m u /
-(1 - m u)): a dense op of k qubits computes each output as a real inner
-product of 2^(k+1) terms, so its error is at most
-    eps_k = (sqrt(2) gamma_(2^(k+1)) + u) * 2^(k/2)
-times the 2-norm of its input (the u term covers the single rounding of the
-matrix to FP32, the 2^(k/2) bounds the 2-norm of |U| for unitary U); a
-diagonal op costs eps_diag = sqrt(2) gamma_2 + u; a +-1 diagonal costs 0.
-A single-qubit gate split into phase * rotation * phase has two diagonal ops
-and one rotation run as three shears S_a S_b S_a (|a|, |b| <= 1, so every
-shear has 2-norm <= phi = (1 + sqrt 5) / 2): rounding a and b to FP32 moves
-the product by <= 3 phi^2 u, and each shear's single FMA rounding (at most
-u sqrt(2) times the norm of the vector it acts on, then carried through the
-remaining shears) adds <= 3 sqrt(2) phi^2 u, so
-    eps_rot = 3 phi^2 (1 + sqrt 2) u (1 + 1e-4) + 2e-14
-per rotated qubit (the last term covers the FP64 factorisation, accepted only
-when it reproduces the gate to 1e-14 per entry).
-Errors of successive (near-)unitary ops add to first order, so
-    ||psi_c64 - psi_exact||_2 <= sum over ops of eps_op   (rigorous bound),
-and max|delta amp| <= ||delta||_2, 1 - fidelity <= ||delta||_2^2.
-The tests assert the measured error is below the rigorous bound and print the
-typical estimate sqrt(sum eps_op^2) beside it.
+FP64 readouts.  Parity is stated per result as the measured ||delta psi||_2
+(and max |delta amp|, 1 - fidelity where the reference state is at hand)
+against two figures from tests/c64_bounds.py: a rigorous first-order bound
+(asserted) and a typical estimate from the probabilistic rounding model
+(asserted with a stated multiple, c64_bounds.TYPICAL_MULTIPLE).
 """
 from __future__ import annotations
 
@@ -33,34 +15,11 @@ import pytest
 from oracle import sim
 from paper_2406_14084_amd import inputs as I
 from paper_2406_14084_amd import qs
+from tests import c64_bounds as B
+from tests.c64_bounds import bound_for
 from tests.gpu_util import need_gpu, say
 
 pytestmark = pytest.mark.gpu
-
-U32 = 2.0 ** -24
-
-
-def gamma(m):
-    return m * U32 / (1 - m * U32)
-
-
-def eps_dense(k):
-    return (math.sqrt(2) * gamma(2 ** (k + 1)) + U32) * 2 ** (k / 2)
-
-
-EPS_DIAG = math.sqrt(2) * gamma(2) + U32
-PHI = (1 + math.sqrt(5)) / 2
-EPS_ROT = 3 * PHI ** 2 * (1 + math.sqrt(2)) * U32 * (1 + 1e-4) + 2e-14
-
-
-def bound_for(plan):
-    s = plan.stats()
-    terms = []
-    for k in range(1, 6):
-        terms += [eps_dense(k)] * s["ops_dense"][k]
-    terms += [EPS_DIAG] * s["ops_diag"]
-    terms += [EPS_ROT] * s["ops_rot"]
-    return sum(terms), math.sqrt(sum(t * t for t in terms))
 
 
 @pytest.fixture(scope="module")
@@ -81,7 +40,7 @@ def test_c64_random_vs_oracle(torch, n, seed, kmax):
     d2 = float(np.linalg.norm(got - want))
     rig, typ = bound_for(p)
     say("||d||2 = %.3e  max|d| = %.3e  bound %.3e (typical %.3e)" % (d2, np.max(np.abs(got - want)), rig, typ))
-    assert d2 <= rig
+    B.check(d2, rig, typ)
 
 
 def test_c64_u3_cz_20q_half_buffer_vs_oracle(torch):
@@ -100,7 +59,7 @@ def test_c64_u3_cz_20q_half_buffer_vs_oracle(torch):
     d2 = float(np.linalg.norm(got - sim.run(c)))
     rig, typ = bound_for(p)
     say("||d||2 = %.3e  bound %.3e (typical %.3e)" % (d2, rig, typ))
-    assert d2 <= rig
+    B.check(d2, rig, typ)
 
 
 def test_c64_u3_cx_20q_vs_oracle(torch):
@@ -118,7 +77,8 @@ def test_c64_u3_cx_20q_vs_oracle(torch):
     fid = abs(np.vdot(want, got)) ** 2 / np.vdot(got, got).real
     say("||d||2 = %.3e  max|d| = %.3e  1-F = %.3e  bound %.3e (typical %.3e)"
         % (d2, np.max(np.abs(got - want)), 1 - fid, rig, typ))
-    assert d2 <= rig and 1 - fid <= rig ** 2 + 1e-12
+    B.check(d2, rig, typ)
+    assert 1 - fid <= rig ** 2 + 1e-12
 
 
 def test_c64_gbg_vs_oracle(torch):
@@ -128,8 +88,10 @@ def test_c64_gbg_vs_oracle(torch):
     st.apply_circuit_gbg(c)
     got = st.numpy().astype(np.complex128)
     want = sim.run(c)
-    rig = sum(eps_dense(g.k) for g in c.gates)
-    assert float(np.linalg.norm(got - want)) <= rig
+    rig, typ = B.bound_gbg(c)
+    d2 = float(np.linalg.norm(got - want))
+    say("gbg c64: ||d||2 = %.3e bound %.3e (typical %.3e)" % (d2, rig, typ))
+    B.check(d2, rig, typ)
 
 
 def test_c64_swap_exact(torch):
@@ -177,7 +139,7 @@ def test_c64_vs_c128_32q(torch):
     fid = abs(ov) ** 2 / nrm
     rig, typ = bound_for(p32)
     say("32q: ||d||2 = %.3e max|d| = %.3e 1-F = %.3e bound %.3e typical %.3e" % (d2, dmax, 1 - fid, rig, typ))
-    assert d2 <= rig
+    B.check(d2, rig, typ)
 
 
 @pytest.mark.parametrize("n,seed,chunk", [(14, 21, 0), (18, 22, 11), (20, 23, 12)])
@@ -204,7 +166,7 @@ def test_c64_matrix_core_ops_vs_oracle(torch, n, seed, chunk):
         rig, typ = bound_for(p)
         say("mfma=%s n=%d ||d||2 = %.3e bound %.3e (typical %.3e) mfma ops %d"
             % (mf, n, d2, rig, typ, p.stats()["ops_mfma"]))
-        assert d2 <= rig
+        B.check(d2, rig, typ)
         out[mf] = (got, rig)
     assert float(np.linalg.norm(out[True][0] - out[False][0])) <= out[True][1] + out[False][1]
 
@@ -223,10 +185,14 @@ def test_c64_max_size_34q_inverse(torch):
     p2 = qs.Plan(c.inverse(), kmax=5, dtype="c64")
     st.apply_plan(p1)
     st.apply_plan(p2)
-    rig = bound_for(p1)[0] + bound_for(p2)[0]
+    (r1, t1), (r2, t2) = bound_for(p1), bound_for(p2)
+    rig, typ = r1 + r2, math.hypot(t1, t2)
     a0 = complex(st.tensor[0].item())
     norm = st.expect([(0, 0, 1.0)])
     # ||psi - e0||^2 = norm - 2 Re a0 + 1, accumulated in FP64 on the GPU
     d2 = math.sqrt(max(0.0, norm - 2 * a0.real + 1.0))
-    say("34q: |a0 - 1| = %.3e  ||psi - e0|| = %.3e  bound %.3e" % (abs(a0 - 1), d2, rig))
+    say("34q: |a0 - 1| = %.3e  ||psi - e0|| = %.3e  bound %.3e (typical %.3e)" % (abs(a0 - 1), d2, rig, typ))
     assert abs(a0 - 1) <= rig and d2 <= rig + 1e-6
+    # the FP64 norm is accumulated from FP32 amplitudes: ||psi - e0|| computed as
+    # sqrt(norm - 2 Re a0 + 1) carries an absolute error of about sqrt(2^34 u^2)
+    B.check(abs(a0 - 1), rig, typ)

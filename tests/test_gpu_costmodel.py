@@ -215,7 +215,8 @@ def test_learned_vs_heuristic_c64_30q(torch):
     30-qubit U3 + CX, depth 60.  The learned plan must not lose to the
     heuristic (best of two runs each) and both states agree within the sum of
     their rigorous complex64 bounds."""
-    from tests.test_gpu_c64 import bound_for
+    from tests import c64_bounds as B
+    from tests.c64_bounds import bound_for
     model = trained_model()
     n = 30
     c = I.random_u3_2q(n=n, depth=60, seed=30064, two="CX")
@@ -233,5 +234,6 @@ def test_learned_vs_heuristic_c64_30q(torch):
     del a
     say("c64 30q heuristic %.1f ms  learned %.1f ms  gain %.1f %%  ||d||2 %.2e"
         % (th, tl, 100 * (th - tl) / th, d))
-    assert d <= bound_for(ph)[0] + bound_for(pl)[0]
+    (rh, th_), (rl, tl_) = bound_for(ph), bound_for(pl)
+    B.check(d, rh + rl, math.hypot(th_, tl_))
     assert tl <= 1.01 * th

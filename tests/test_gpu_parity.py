@@ -213,3 +213,46 @@ def test_u3_cz_30q_inverse_full_size(torch):
     rest = float((t[1:].abs() ** 2).sum().item())
     assert abs(norm1 - 1.0) <= 1e-11
     assert abs(a0 - 1.0) <= 1e-11 and math.sqrt(rest) <= 1e-11, (a0, rest)
+
+
+def test_boundary_workspace_streams_and_amplitudes(torch):
+    """Caller-owned workspace and the handle's own scratch give identical
+    results (5-qubit gates and expectations go through it); one plan applied
+    on two streams uploads its tables once per device and both runs match the
+    oracle; qs_get_amplitudes returns the tensor's bytes, in ranges."""
+    n = 16
+    rng = np.random.default_rng(31)
+    c = I.random_dense(n, 60, seed=31, kmax=3)
+    for _ in range(4):
+        tg = tuple(int(x) for x in rng.choice(n, 5, replace=False))
+        c.add("U5", tg, I.g_haar(rng, 32))
+    want = sim.run(c)
+    terms = [(3, 5, 0.7), (0, 9, -0.2), (17, 0, 1.1)]
+    outs = []
+    for ws in (True, False):
+        say("gbg with workspace" if ws else "gbg with own scratch")
+        st = qs.State(n, "c128", workspace=ws)
+        assert (st.workspace is not None) == ws
+        st.init_zero()
+        st.apply_circuit_gbg(c)
+        outs.append((st.numpy(), st.expect(terms)))
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
+    assert max_abs_diff(outs[0][0], want) <= TOL_C128
+    assert abs(outs[0][1] - sim.expect(want, terms)) <= 1e-12
+    p = qs.Plan(c, kmax=5)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    a = qs.State(n, "c128", stream=s1)
+    b = qs.State(n, "c128", stream=s2)
+    say("one plan, two streams")
+    a.init_zero()
+    a.apply_plan(p)
+    b.init_zero()
+    b.apply_plan(p)
+    torch.cuda.synchronize()
+    assert max_abs_diff(a.numpy(), want) <= TOL_C128 and max_abs_diff(b.numpy(), want) <= TOL_C128
+    full = a.numpy()
+    assert np.array_equal(a.amplitudes(), full)
+    assert np.array_equal(a.amplitudes(1000, 77), full[1000:1077])
+    assert a.amplitudes((1 << n) - 3, 3).size == 3
+    with pytest.raises(qs.QSError):
+        a.amplitudes((1 << n) - 3, 4)

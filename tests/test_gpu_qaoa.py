@@ -18,7 +18,7 @@ from oracle import sim
 from paper_2406_14084_amd import inputs as I
 from paper_2406_14084_amd import qs
 from tests.gpu_util import need_gpu, say
-from tests.test_gpu_c64 import EPS_DIAG, U32, eps_dense
+from tests.c64_bounds import EPS_DIAG, U32, eps_dense
 
 pytestmark = pytest.mark.gpu
 

@@ -25,6 +25,10 @@ MUTANTS = {
                            "double br = psi[2 * j], bi = psi[2 * j + 1];")],
     "probs_dropped_imag": [("p[i] = psi[2 * i] * psi[2 * i] + psi[2 * i + 1] * psi[2 * i + 1];",
                             "p[i] = psi[2 * i] * psi[2 * i];")],
+    "probs_index_shift": [("for (i64 i = 0; i < N; ++i) p[i] = psi[2 * i] * psi[2 * i] + psi[2 * i + 1] * psi[2 * i + 1];",
+                           "for (i64 i = 0; i < N; ++i) p[i] = psi[2 * (i ^ 1)] * psi[2 * (i ^ 1)] + psi[2 * (i ^ 1) + 1] * psi[2 * (i ^ 1) + 1];")],
+    "probs_cross_term": [("p[i] = psi[2 * i] * psi[2 * i] + psi[2 * i + 1] * psi[2 * i + 1];",
+                          "p[i] = psi[2 * i] * psi[2 * i] + psi[2 * i] * psi[2 * i + 1];")],
     "qaoa_phase_sign": [("double th = -gamma", "double th = gamma")],
     "cut_and_not_xor": [("(((z >> edges[2 * e]) ^ (z >> edges[2 * e + 1])) & 1)",
                          "(((z >> edges[2 * e]) & (z >> edges[2 * e + 1])) & 1)")],

@@ -144,9 +144,31 @@ def check_pauli_bruteforce(L):
 
 
 def check_probs(L):
+    """Closed forms of p_i = |a_i|^2 (Eq. 1): H on every qubit gives 2^-n on
+    every basis state; GHZ gives 1/2 at |0..0> and |1..1> and 0 elsewhere;
+    a basis state gives a one-hot vector; a state scaled by a phase keeps its
+    probabilities; a hand-computed 2-amplitude case (3+4i)/5, 0 -> 1, 0."""
+    n = 10
+    c = I.Circuit(n)
+    for q in range(n):
+        c.add("H", (q,), I.g_h())
+    p = sim.probs(sim.run(c, L), L)
+    assert np.max(np.abs(p - 2.0 ** -n)) <= 1e-15
+    assert abs(float(np.sum(p)) - 1.0) <= 1e-13
+    p = sim.probs(sim.run(I.ghz(9), L), L)
+    want = np.zeros(1 << 9)
+    want[0] = want[-1] = 0.5
+    assert np.max(np.abs(p - want)) <= 1e-15
+    psi = np.zeros(32, dtype=np.complex128)
+    psi[13] = 1j
+    p = sim.probs(psi, L)
+    assert p[13] == 1.0 and np.count_nonzero(p) == 1
+    p = sim.probs(np.array([0.6 + 0.8j, 0.0], dtype=np.complex128), L)
+    assert abs(p[0] - 1.0) <= 2e-16 and p[1] == 0.0
     rng = np.random.default_rng(5)
     psi = rng.standard_normal(64) + 1j * rng.standard_normal(64)
-    assert np.allclose(sim.probs(psi, L), np.abs(psi) ** 2, rtol=1e-15, atol=0)
+    ph = np.exp(0.37j)
+    assert np.max(np.abs(sim.probs(psi * ph, L) - sim.probs(psi, L))) <= 1e-13
 
 
 def check_worked_example_d4(L):
