@@ -166,6 +166,18 @@ QS_API qs_status qs_init_basis(qs_state *st, uint64_t index);
  * copied before return.  Async. */
 QS_API qs_status qs_apply_gate(qs_state *st, int k, const int *targets, const double *matrix);
 
+/* How qs_apply_gate runs a gate (host only, no state needed): qubits on
+ * which the matrix acts as the identity unless the qubit is 1 are controls
+ * (*ctrl_mask, qubit numbers as bits) and the pass visits only amplitudes
+ * with every control set; on the *active remaining targets the matrix is
+ * *kind = 0 dense, 1 diagonal (only entries different from 1 are applied:
+ * CZ and CP touch a quarter of the state), 2 a permutation with phases (only
+ * rows that move or change are written; with unit phases no arithmetic: CX
+ * and SWAP move half the state).  Paper: Sec. VI-D (gates that touch less of
+ * the state, or do no floating-point work, run faster), Eq. 2 / Eq. 3. */
+QS_API qs_status qs_gate_class(int k, const int *targets, const double *matrix, int *kind, uint64_t *ctrl_mask,
+                               int *active);
+
 /* In-memory swap of qubit sets (Eq. 4, Alg. 4): exchange index bits a[j] and
  * b[j] for j < s (all 2s qubits distinct, s <= 8).  One pass.  Async. */
 QS_API qs_status qs_swap_qubits(qs_state *st, int s, const int *a, const int *b);

@@ -189,22 +189,7 @@ qs_status qs_apply_gate(qs_state *st, int k, const int *targets, const double *m
         }
         seen |= 1ull << targets[j];
     }
-    const void *dmat = nullptr;
-    if (k >= 4) {
-        // matrix goes through the scratch buffer, in stream order
-        const size_t cnt = 2u << (2 * k);
-        if (st->dtype == QS_C64) {
-            std::vector<float> m32(cnt);
-            for (size_t i = 0; i < cnt; ++i) m32[i] = (float)matrix[i];
-            QS_CHECK_HIP(hipMemcpyAsync(st->d_scratch, m32.data(), cnt * 4, hipMemcpyHostToDevice, st->stream), "qs_apply_gate: upload");
-            QS_CHECK_HIP(hipStreamSynchronize(st->stream), "qs_apply_gate: sync");
-        } else {
-            QS_CHECK_HIP(hipMemcpyAsync(st->d_scratch, matrix, cnt * 8, hipMemcpyHostToDevice, st->stream), "qs_apply_gate: upload");
-            QS_CHECK_HIP(hipStreamSynchronize(st->stream), "qs_apply_gate: sync");
-        }
-        dmat = st->d_scratch;
-    }
-    QS_CHECK_HIP(qs::launch_gate(st, k, targets, matrix, dmat), "qs_apply_gate: launch");
+    QS_CHECK_HIP(qs::launch_gate(st, k, targets, matrix), "qs_apply_gate: launch");
     return QS_OK;
 }
 
@@ -218,6 +203,18 @@ static qs_status run_blocks(qs_state *st, const qs::Plan &p, const int *d_prog, 
                                              p.block_mfma[b] != 0, (p.h_prog[p.prog_off[b] + 3] & 4) != 0);
         if (e != hipSuccess) return hip_fail(e, fn);
     }
+    return QS_OK;
+}
+
+qs_status qs_gate_class(int k, const int *targets, const double *matrix, int *kind, uint64_t *ctrl_mask, int *active)
+{
+    if (k < 1 || k > 5 || !targets || !matrix || !kind) { set_error("qs_gate_class: k must be 1..5, arrays non-null"); return QS_EINVAL; }
+    uint64_t seen = 0;
+    for (int j = 0; j < k; ++j) {
+        if (targets[j] < 0 || targets[j] > 63 || ((seen >> targets[j]) & 1)) { set_error("qs_gate_class: bad or repeated target"); return QS_EINVAL; }
+        seen |= 1ull << targets[j];
+    }
+    *kind = qs::gate_kind(k, targets, matrix, ctrl_mask, active);
     return QS_OK;
 }
 

@@ -4,6 +4,7 @@
 // Paper: Eq. 1 (state, probabilities), Eq. 2 / Eq. 3 (gate application, the
 // gate-by-gate scheme the blocked path is compared with, Sec. V-A / VI-F).
 #include <algorithm>
+#include <vector>
 
 #include "amp.h"
 #include "qs_internal.h"
@@ -25,27 +26,41 @@ __global__ __launch_bounds__(256) void k_init(typename AmpOf<F>::type *__restric
     }
 }
 
-// Gate matrix passed by value (k <= 3): 2 * 4^k scalars.
+// Gate-by-gate kernels (one pass per gate, Eq. 2 / Eq. 3).  The host
+// classifies each gate first (classify_gate): qubits on which the matrix is
+// the identity unless the qubit is 1 are controls -- the pass then visits only
+// the tuples with every control bit set; on the remaining K targets the
+// matrix is diagonal (only the entries that differ from 1 are multiplied:
+// CZ and CP touch a quarter of the state), a permutation with phases (only
+// the rows that move or change are written; unit phases are pure data
+// movement: CX moves half the state, SWAP half, X all of it) or dense.
+// A tuple is the 2^K amplitudes base | off[c], base having zeros at every
+// target and control position and ones at the controls.
+constexpr int kMaxGateBits = 10;
+
+struct TupleIndex {
+    int nz;                        // targets + controls
+    int zs[kMaxGateBits];          // their positions, ascending
+    uint64_t cbits;                // control bits (all set in every visited tuple)
+};
+
+__device__ __forceinline__ uint64_t tuple_base(uint64_t j, const TupleIndex &t)
+{
+    for (int i = 0; i < t.nz; ++i) {
+        const uint64_t lo = j & ((1ull << t.zs[i]) - 1);
+        j = ((j >> t.zs[i]) << (t.zs[i] + 1)) | lo;
+    }
+    return j | t.cbits;
+}
+
+// Dense K-qubit matrix passed by value (K <= 3): 2 * 4^K scalars.
 template <int K, typename F>
 struct GateArgs {
+    TupleIndex ti;
     uint64_t off[1 << K];      // physical offset of local index c (circuit convention)
-    int tsorted[K];            // target qubits ascending (for zero insertion)
     F m[2 << (2 * K)];
 };
 
-template <int K, typename F>
-__device__ __forceinline__ uint64_t insert_zeros(uint64_t j, const int *ts)
-{
-    // ts ascending: open a zero at each target position
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-        const uint64_t lo = j & ((1ull << ts[i]) - 1);
-        j = ((j >> ts[i]) << (ts[i] + 1)) | lo;
-    }
-    return j;
-}
-
-// One thread per 2^K-tuple: gather, multiply by the gate matrix, scatter.
 template <int K, typename F>
 __global__ __launch_bounds__(256) void k_gate_val(typename AmpOf<F>::type *__restrict__ a, uint64_t ntuples,
                                                  GateArgs<K, F> g)
@@ -55,7 +70,7 @@ __global__ __launch_bounds__(256) void k_gate_val(typename AmpOf<F>::type *__res
     uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (; j < ntuples; j += stride) {
-        const uint64_t base = insert_zeros<K, F>(j, g.tsorted);
+        const uint64_t base = tuple_base(j, g.ti);
         V in[D];
 #pragma unroll
         for (int c = 0; c < D; ++c) in[c] = a[base | g.off[c]];
@@ -69,11 +84,11 @@ __global__ __launch_bounds__(256) void k_gate_val(typename AmpOf<F>::type *__res
     }
 }
 
-// k = 4, 5: matrix in device memory (scratch), offsets by value.
+// K = 4, 5 dense: matrix in device memory (the workspace), offsets by value.
 template <int K>
 struct GateOffs {
+    TupleIndex ti;
     uint64_t off[1 << K];
-    int tsorted[K];
 };
 
 template <int K, typename F>
@@ -85,7 +100,7 @@ __global__ __launch_bounds__(256) void k_gate_ptr(typename AmpOf<F>::type *__res
     uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (; j < ntuples; j += stride) {
-        const uint64_t base = insert_zeros<K, F>(j, g.tsorted);
+        const uint64_t base = tuple_base(j, g.ti);
         V in[D];
 #pragma unroll
         for (int c = 0; c < D; ++c) in[c] = a[base | g.off[c]];
@@ -94,6 +109,44 @@ __global__ __launch_bounds__(256) void k_gate_ptr(typename AmpOf<F>::type *__res
 #pragma unroll
             for (int c = 1; c < D; ++c) cmac<F, V>(acc, m[2 * (r * D + c)], m[2 * (r * D + c) + 1], in[c]);
             a[base | g.off[r]] = acc;
+        }
+    }
+}
+
+// Diagonal or permutation-with-phases on K <= 5 targets.  Only the nact
+// active rows are touched: row r gets e[r] * a[base | off[src[r]]] (src[r] = r
+// for a diagonal); unit = 1 when every e[r] is exactly 1 (a pure move).
+struct GateSparse {
+    TupleIndex ti;
+    int nact;
+    int unit;
+    uint64_t off[32];          // off[i]: offset of active row i
+    uint64_t soff[32];         // offset of its source column
+    double e[64];              // its coefficient (re, im), FP64 (rounded to the state precision in the kernel)
+};
+
+template <int NMAX, typename F>
+__global__ __launch_bounds__(256) void k_gate_sparse(typename AmpOf<F>::type *__restrict__ a, uint64_t ntuples,
+                                                    GateSparse g)
+{
+    using V = typename AmpOf<F>::type;
+    uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (; j < ntuples; j += stride) {
+        const uint64_t base = tuple_base(j, g.ti);
+        V in[NMAX];
+        // every source is read before any row is written (a permutation may
+        // write a row another row reads)
+#pragma unroll
+        for (int i = 0; i < NMAX; ++i)
+            if (i < g.nact) in[i] = a[base | g.soff[i]];
+#pragma unroll
+        for (int i = 0; i < NMAX; ++i) {
+            if (i < g.nact) {
+                V v = in[i];
+                if (!g.unit) v = cmul<F, V>((F)g.e[2 * i], (F)g.e[2 * i + 1], v);
+                a[base | g.off[i]] = v;
+            }
         }
     }
 }
@@ -157,45 +210,173 @@ unsigned grid_for(uint64_t items, unsigned threads, unsigned cap)
     return (unsigned)g;
 }
 
+// Host classification of a k-qubit gate (targets t[0..k-1], t[0] = MSB of the
+// local index) into controls and an active kind on the remaining targets.
+struct GateClass {
+    int kind = 0;                 // 0 dense, 1 diagonal, 2 permutation with phases
+    int nt = 0;                   // active targets
+    int tq[5];                    // their qubits, t[0] = MSB of the sub-matrix index
+    uint64_t cbits = 0;           // control qubits (mask)
+    std::vector<cplx> u;          // 2^nt x 2^nt sub-matrix (row-major)
+};
+
+GateClass classify_gate(int k, const int *targets, const double *matrix)
+{
+    const int D = 1 << k;
+    auto M = [&](int r, int c) { return cplx(matrix[2 * (r * D + c)], matrix[2 * (r * D + c) + 1]); };
+    // local bit of target j is k-1-j; a control bit b: rows/columns with b = 0
+    // form an identity block and nothing mixes the b = 0 and b = 1 halves
+    int cmask = 0;   // local bits found to be controls
+    for (int b = k - 1; b >= 0; --b) {
+        bool ctrl = true;
+        for (int r = 0; r < D && ctrl; ++r) {
+            if ((r & cmask) != cmask) continue;
+            for (int c = 0; c < D && ctrl; ++c) {
+                if ((c & cmask) != cmask) continue;
+                const bool rb = (r >> b) & 1, cb = (c >> b) & 1;
+                const cplx v = M(r, c);
+                if (rb != cb) ctrl = (v == cplx(0, 0));
+                else if (!rb) {
+                    // b = 0 half: identity, and no mixing with other local indices
+                    ctrl = (r == c) ? (v == cplx(1, 0)) : (v == cplx(0, 0));
+                }
+            }
+        }
+        // at least one active target must remain
+        if (ctrl && __builtin_popcount(cmask | (1 << b)) < k) cmask |= 1 << b;
+    }
+    GateClass g;
+    for (int j = 0; j < k; ++j) {
+        const int b = k - 1 - j;
+        if ((cmask >> b) & 1) g.cbits |= 1ull << targets[j];
+        else g.tq[g.nt++] = targets[j];
+    }
+    const int d = 1 << g.nt;
+    // sub-matrix on the active targets (controls fixed to 1)
+    int lb[5], m = 0;      // local bit of active target i (i = 0 is the sub-matrix MSB)
+    for (int j = 0; j < k; ++j)
+        if (!((cmask >> (k - 1 - j)) & 1)) lb[m++] = k - 1 - j;
+    auto lift = [&](int s) {
+        int r = cmask;
+        for (int i = 0; i < g.nt; ++i)
+            if ((s >> (g.nt - 1 - i)) & 1) r |= 1 << lb[i];
+        return r;
+    };
+    g.u.resize((size_t)d * d);
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c) g.u[(size_t)r * d + c] = M(lift(r), lift(c));
+    bool diag = true, perm = true;
+    for (int r = 0; r < d; ++r) {
+        int nz = 0;
+        for (int c = 0; c < d; ++c)
+            if (g.u[(size_t)r * d + c] != cplx(0, 0)) {
+                ++nz;
+                if (c != r) diag = false;
+            }
+        if (nz != 1) perm = false;
+    }
+    if (perm) {
+        for (int c = 0; c < d && perm; ++c) {
+            int nz = 0;
+            for (int r = 0; r < d; ++r) nz += g.u[(size_t)r * d + c] != cplx(0, 0);
+            if (nz != 1) perm = false;
+        }
+    }
+    g.kind = (diag && perm) ? 1 : perm ? 2 : 0;
+    return g;
+}
+
 template <typename F>
-hipError_t gate_F(qs_state *st, int k, const int *targets, const double *matrix, const void *d_matrix)
+hipError_t gate_F(qs_state *st, int k, const int *targets, const double *matrix)
 {
     using V = typename AmpOf<F>::type;
-    const uint64_t ntuples = 1ull << (st->n - k);
-    const unsigned grid = grid_for(ntuples, 256, 256u * 1024u);
     V *a = reinterpret_cast<V *>(st->amps);
-    int ts[5];
-    for (int j = 0; j < k; ++j) ts[j] = targets[j];
-    std::sort(ts, ts + k);
-    auto fill_off = [&](uint64_t *off) {
-        for (int c = 0; c < (1 << k); ++c) {
-            uint64_t o = 0;
-            for (int j = 0; j < k; ++j)
-                if ((c >> (k - 1 - j)) & 1) o |= 1ull << targets[j];
-            off[c] = o;
-        }
+    const GateClass g = classify_gate(k, targets, matrix);
+    const int nc = __builtin_popcountll(g.cbits);
+    const uint64_t ntuples = 1ull << (st->n - g.nt - nc);
+    const unsigned grid = grid_for(ntuples, 256, 256u * 1024u);
+    const int d = 1 << g.nt;
+    TupleIndex ti;
+    ti.nz = 0;
+    for (int q = 0; q < st->n; ++q) {
+        bool used = (g.cbits >> q) & 1;
+        for (int i = 0; i < g.nt; ++i) used = used || g.tq[i] == q;
+        if (used) ti.zs[ti.nz++] = q;
+    }
+    ti.cbits = g.cbits;
+    auto offset = [&](int c) {
+        uint64_t o = 0;
+        for (int i = 0; i < g.nt; ++i)
+            if ((c >> (g.nt - 1 - i)) & 1) o |= 1ull << g.tq[i];
+        return o;
     };
-    switch (k) {
+    if (g.kind != 0) {
+        GateSparse s;
+        s.ti = ti;
+        s.nact = 0;
+        s.unit = 1;
+        for (int r = 0; r < d; ++r) {
+            int src = r;
+            for (int c = 0; c < d; ++c)
+                if (g.u[(size_t)r * d + c] != cplx(0, 0)) src = c;
+            const cplx e = g.u[(size_t)r * d + src];
+            if (src == r && e == cplx(1, 0)) continue;     // row unchanged
+            s.off[s.nact] = offset(r);
+            s.soff[s.nact] = offset(src);
+            s.e[2 * s.nact] = e.real();
+            s.e[2 * s.nact + 1] = e.imag();
+            if (e != cplx(1, 0)) s.unit = 0;
+            ++s.nact;
+        }
+        if (s.nact == 0) return hipSuccess;               // the identity
+        if (s.nact <= 1) hipLaunchKernelGGL((k_gate_sparse<1, F>), dim3(grid), dim3(256), 0, st->stream, a, ntuples, s);
+        else if (s.nact <= 2) hipLaunchKernelGGL((k_gate_sparse<2, F>), dim3(grid), dim3(256), 0, st->stream, a, ntuples, s);
+        else if (s.nact <= 4) hipLaunchKernelGGL((k_gate_sparse<4, F>), dim3(grid), dim3(256), 0, st->stream, a, ntuples, s);
+        else if (s.nact <= 8) hipLaunchKernelGGL((k_gate_sparse<8, F>), dim3(grid), dim3(256), 0, st->stream, a, ntuples, s);
+        else if (s.nact <= 16) hipLaunchKernelGGL((k_gate_sparse<16, F>), dim3(grid), dim3(256), 0, st->stream, a, ntuples, s);
+        else hipLaunchKernelGGL((k_gate_sparse<32, F>), dim3(grid), dim3(256), 0, st->stream, a, ntuples, s);
+        return hipGetLastError();
+    }
+    switch (g.nt) {
 #define QS_GATE_VAL(KK)                                                                                  \
     case KK: {                                                                                           \
-        GateArgs<KK, F> g;                                                                               \
-        fill_off(g.off);                                                                                 \
-        for (int j = 0; j < KK; ++j) g.tsorted[j] = ts[j];                                               \
-        for (int i = 0; i < (2 << (2 * KK)); ++i) g.m[i] = (F)matrix[i];                                 \
-        hipLaunchKernelGGL((k_gate_val<KK, F>), dim3(grid), dim3(256), 0, st->stream, a, ntuples, g);   \
+        GateArgs<KK, F> ga;                                                                              \
+        ga.ti = ti;                                                                                      \
+        for (int c = 0; c < (1 << KK); ++c) ga.off[c] = offset(c);                                       \
+        for (int i = 0; i < (1 << (2 * KK)); ++i) {                                                      \
+            ga.m[2 * i] = (F)g.u[i].real();                                                              \
+            ga.m[2 * i + 1] = (F)g.u[i].imag();                                                          \
+        }                                                                                                \
+        hipLaunchKernelGGL((k_gate_val<KK, F>), dim3(grid), dim3(256), 0, st->stream, a, ntuples, ga);  \
         return hipGetLastError();                                                                        \
     }
         QS_GATE_VAL(1)
         QS_GATE_VAL(2)
         QS_GATE_VAL(3)
 #undef QS_GATE_VAL
+    default:
+        break;
+    }
+    // 4-5 active targets: the sub-matrix goes through the workspace, in stream order
+    const size_t cnt = (size_t)2 * d * d;
+    std::vector<F> mw(cnt);
+    for (size_t i = 0; i < (size_t)d * d; ++i) {
+        mw[2 * i] = (F)g.u[i].real();
+        mw[2 * i + 1] = (F)g.u[i].imag();
+    }
+    if (cnt * sizeof(F) > st->scratch_bytes) return hipErrorInvalidValue;
+    hipError_t e = hipMemcpyAsync(st->d_scratch, mw.data(), cnt * sizeof(F), hipMemcpyHostToDevice, st->stream);
+    // the host buffer must outlive the copy
+    if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+    if (e != hipSuccess) return e;
+    const F *dm = reinterpret_cast<const F *>(st->d_scratch);
+    switch (g.nt) {
 #define QS_GATE_PTR(KK)                                                                                  \
     case KK: {                                                                                           \
-        GateOffs<KK> g;                                                                                  \
-        fill_off(g.off);                                                                                 \
-        for (int j = 0; j < KK; ++j) g.tsorted[j] = ts[j];                                               \
-        hipLaunchKernelGGL((k_gate_ptr<KK, F>), dim3(grid), dim3(256), 0, st->stream, a, ntuples, g,     \
-                           reinterpret_cast<const F *>(d_matrix));                                       \
+        GateOffs<KK> go;                                                                                 \
+        go.ti = ti;                                                                                      \
+        for (int c = 0; c < (1 << KK); ++c) go.off[c] = offset(c);                                       \
+        hipLaunchKernelGGL((k_gate_ptr<KK, F>), dim3(grid), dim3(256), 0, st->stream, a, ntuples, go, dm); \
         return hipGetLastError();                                                                        \
     }
         QS_GATE_PTR(4)
@@ -219,10 +400,18 @@ hipError_t launch_init(qs_state *st, uint64_t index)
     return hipGetLastError();
 }
 
-hipError_t launch_gate(qs_state *st, int k, const int *targets, const double *matrix, const void *d_matrix)
+hipError_t launch_gate(qs_state *st, int k, const int *targets, const double *matrix)
 {
-    if (st->dtype == QS_C64) return gate_F<float>(st, k, targets, matrix, d_matrix);
-    return gate_F<double>(st, k, targets, matrix, d_matrix);
+    if (st->dtype == QS_C64) return gate_F<float>(st, k, targets, matrix);
+    return gate_F<double>(st, k, targets, matrix);
+}
+
+int gate_kind(int k, const int *targets, const double *matrix, uint64_t *cbits, int *nt)
+{
+    const GateClass g = classify_gate(k, targets, matrix);
+    if (cbits) *cbits = g.cbits;
+    if (nt) *nt = g.nt;
+    return g.kind;
 }
 
 hipError_t launch_probs(qs_state *st, double *out)

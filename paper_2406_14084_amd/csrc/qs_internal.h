@@ -186,7 +186,10 @@ qs_status hip_fail(hipError_t e, const char *what);
 // kernel launchers (k_basic.hip / k_block.hip)
 namespace qs {
 hipError_t launch_init(qs_state *st, uint64_t index);
-hipError_t launch_gate(qs_state *st, int k, const int *targets, const double *matrix, const void *d_matrix);
+hipError_t launch_gate(qs_state *st, int k, const int *targets, const double *matrix);
+// gate-by-gate kind of a gate: 0 dense, 1 diagonal, 2 permutation with phases, on *nt
+// active targets once the controls in *cbits are peeled off (host only)
+int gate_kind(int k, const int *targets, const double *matrix, uint64_t *cbits, int *nt);
 hipError_t launch_swap(qs_state *st, int s, const int *a, const int *b);
 hipError_t launch_probs(qs_state *st, double *out);
 hipError_t launch_expect(qs_state *st, int nterms, const qs_pauli *terms, double *partials, int nparts);

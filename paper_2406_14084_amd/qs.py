@@ -71,6 +71,8 @@ SIGNATURES = {
     "qs_init_basis": (C.c_int, [_P, C.c_uint64]),
     "qs_apply_gate": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "qs_swap_qubits": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "qs_gate_class": (C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_int),
+                                C.POINTER(C.c_uint64), C.POINTER(C.c_int)]),
     "qs_fuse": (C.c_int, [C.POINTER(Circuit_C), C.c_int, C.POINTER(PlanOpts_C), C.POINTER(_P)]),
     "qs_apply_plan": (C.c_int, [_P, _P]),
     "qs_apply_plan_timed": (C.c_int, [_P, _P, C.POINTER(C.c_float), C.POINTER(C.c_int), C.c_int]),
@@ -142,6 +144,16 @@ def _stream_ptr(stream):
     torch = _torch()
     s = stream if stream is not None else torch.cuda.current_stream()
     return C.c_void_p(s.cuda_stream)
+
+
+def gate_class(targets, matrix):
+    """(kind, control qubits, active targets) of a gate as the gate-by-gate
+    path runs it: kind 0 dense, 1 diagonal, 2 permutation with phases."""
+    t = np.ascontiguousarray(targets, dtype=np.int32)
+    m = np.ascontiguousarray(np.asarray(matrix, dtype=np.complex128)).view(np.float64)
+    kind, cm, act = C.c_int(), C.c_uint64(), C.c_int()
+    check(lib().qs_gate_class(len(t), _ip(t), _dp(m), C.byref(kind), C.byref(cm), C.byref(act)))
+    return kind.value, [q for q in range(64) if (cm.value >> q) & 1], act.value
 
 
 class State:

@@ -256,3 +256,63 @@ def test_boundary_workspace_streams_and_amplitudes(torch):
     assert a.amplitudes((1 << n) - 3, 3).size == 3
     with pytest.raises(qs.QSError):
         a.amplitudes((1 << n) - 3, 4)
+
+
+def _controlled(u, nctrl):
+    d = u.shape[0]
+    m = np.eye(d << nctrl, dtype=np.complex128)
+    m[-d:, -d:] = u
+    return m
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_gbg_op_kinds_vs_oracle(torch, dtype):
+    """Gate-by-gate op kinds: diagonal (Z, RZ, CZ, CP, RZZ, controlled
+    diagonals), permutation (X, CX, SWAP, CCX, Y with phases), controlled
+    dense (CU, 2-control 2-target, 1-control 4-target) and plain dense, each
+    kind against the oracle on a random state; pure data movement is exact
+    (bit for bit) in both precisions."""
+    n = 15
+    rng = np.random.default_rng(12)
+    psi0 = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    psi0 /= np.linalg.norm(psi0)
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    if dtype == "c64":
+        psi0 = psi0.astype(np.complex64).astype(np.complex128)
+    perm = [("X", (3,), I.g_x()), ("CX", (14, 0), I.g_cx()), ("SWAP", (2, 11), I.g_swap()),
+            ("CCX", (7, 1, 12), _controlled(I.g_x(), 2)), ("CX_lo", (0, 9), I.g_cx())]
+    other = [("Z", (5,), I.g_z()), ("RZ", (13,), I.g_rz(0.7)), ("CZ", (4, 10), I.g_cz()),
+             ("CP", (0, 14), I.g_cp(1.3)), ("RZZ", (6, 8), I.g_rzz(0.9)),
+             ("CCP", (1, 2, 3), _controlled(np.diag([1, np.exp(0.4j)]), 2)),
+             ("Y", (9,), I.g_y()), ("CU", (12, 3), _controlled(I.g_haar(rng, 2), 1)),
+             ("C2U2", (0, 13, 5, 7), _controlled(I.g_haar(rng, 4), 2)),
+             ("CU4", (10, 1, 4, 6, 14), _controlled(I.g_haar(rng, 16), 1)),
+             ("U3", (1, 6, 11), I.g_haar(rng, 8))]
+    for name, tg, m in perm + other:
+        kind, ctrl, act = qs.gate_class(tg, m)
+        say("gbg kind", dtype, name, kind, ctrl, act)
+        st = qs.State(n, dtype)
+        st.tensor.copy_(torch.from_numpy(psi0).to(tdt))
+        st.apply_gate(tg, m)
+        got = st.numpy().astype(np.complex128)
+        want = psi0.copy()
+        sim.apply_gate(want, tg, m)
+        if name in [p[0] for p in perm]:
+            assert kind == 2 and np.array_equal(got, want), name
+        elif dtype == "c128":
+            assert max_abs_diff(got, want) <= TOL_C128, name
+        else:
+            assert max_abs_diff(got, want) <= 1e-6, name
+
+
+def test_gbg_op_kinds_circuit(torch):
+    """The benchmark's U3 + CZ recipe gate by gate (CZ through the diagonal
+    kind) and a U3 + CX circuit (CX through the permutation kind) against the
+    oracle at 20 qubits."""
+    for two in ("CZ", "CX"):
+        c = I.random_u3_2q(n=20, depth=6, seed=2040, two=two)
+        say("gbg circuit", two)
+        st = qs.State(20, "c128")
+        st.init_zero()
+        st.apply_circuit_gbg(c)
+        assert max_abs_diff(st.numpy(), sim.run(c)) <= TOL_C128, two
