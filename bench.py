@@ -34,6 +34,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X published HBM3E bandwidth
 FP64_PEAK_TFLOPS = 78.6      # MI355X published FP64 vector (= matrix) rate
+FP32_PEAK_TFLOPS = 157.3     # MI355X published FP32 rate
 WORKLOAD = dict(n=30, depth=40, seed=30002, kmax=5)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_block_traffic_u3cz30.txt")
 TRAFFIC_SOURCES = ("paper_2406_14084_amd/csrc/k_block.hip", "paper_2406_14084_amd/csrc/planner.cpp")
@@ -97,6 +98,49 @@ def cpu_baseline(circ, max_gates, budget_s):
             "seconds": dt}
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_C1_SCRIPT = r"""
+import sys, time, json
+sys.path.insert(0, %r)
+from oracle import sim
+from paper_2406_14084_amd import inputs as I
+c = I.layered_rotations(n=16, layers=20, seed=16001)
+L = sim.lib()
+psi = sim.zero_state(16)
+t = time.perf_counter()
+sim.apply_circuit(psi, c, L)
+dt = time.perf_counter() - t
+print(json.dumps({"seconds": dt, "gates": len(c), "threads": sim.num_threads(L)}))
+"""
+
+
+def cpu_c1_full():
+    """The oracle on the whole 16-qubit layered circuit (470 gates), in a
+    child process with one OpenMP thread and with the default (all)."""
+    import subprocess
+    out = {}
+    for label, env_threads in (("one_thread", "1"), ("all_threads", None)):
+        env = dict(os.environ)
+        if env_threads:
+            env["OMP_NUM_THREADS"] = env_threads
+        r = subprocess.run([sys.executable, "-c", _C1_SCRIPT % ROOT], capture_output=True, text=True, env=env,
+                           timeout=300)
+        d = json.loads(r.stdout.strip().splitlines()[-1])
+        out[label] = {"gate_applications_per_s": round(d["gates"] / d["seconds"], 1), "seconds": round(d["seconds"], 4),
+                      "threads": d["threads"]}
+    return out
+
+
 def _ms(torch, fn, reps=2):
     best = float("inf")
     for _ in range(reps):
@@ -112,35 +156,61 @@ def _ms(torch, fn, reps=2):
 
 def bench_c64(torch, I, qs):
     """32-qubit complex64 U3 + CX depth 60: matrix-core ops vs vector FMA only;
-    the rigorous state-error bound of the plan beside it."""
+    each with its roofline fraction (HBM bytes at 8 TB/s vs its arithmetic at
+    the FP32 peak, per pass) and its measured error against the same circuit
+    run in complex128 on the GPU (||delta psi||_2, max |delta amp|, 1 - F),
+    beside the rigorous bound and the typical estimate of the plan."""
+    from tests import c64_bounds as B
     n = 32
     c = I.random_u3_2q(n=n, depth=60, seed=32003, two="CX")
-    st = qs.State(n, "c64")
     res = {"workload": "random U3 + CX(random perfect matching), 32 qubits, depth 60, seed 32003, complex64",
            "gates": len(c)}
-    u = 2.0 ** -24
-    gam = lambda m: m * u / (1 - m * u)
+    ref = qs.State(n, "c128")
+    ref.init_zero()
+    ref.apply_plan(qs.Plan(c, kmax=5))
+    st = qs.State(n, "c64")
+    pass_bytes = 2.0 * (1 << n) * 8
     for name, mf in (("mfma", True), ("vector", False)):
         p = qs.Plan(c, kmax=5, dtype="c64", mfma=mf)
         s = p.stats()
         ms = _ms(torch, lambda: (st.init_zero(), st.apply_plan(p)))
-        phi = (1 + math.sqrt(5)) / 2
-        bound = sum(s["ops_dense"][k] * (math.sqrt(2) * gam(2 ** (k + 1)) + u) * 2 ** (k / 2) for k in range(1, 6)) \
-            + s["ops_diag"] * (math.sqrt(2) * gam(2) + u) \
-            + s["ops_rot"] * (3 * phi ** 2 * (1 + math.sqrt(2)) * u * (1 + 1e-4) + 2e-14)
+        ms_steps, kinds = st.apply_plan_timed(p)
+        passes = s["blocks"] + s["swap_passes"]
+        t_roof = max(passes * pass_bytes / (HBM_PEAK_GBS * 1e9), s["flops_per_amp"] * (1 << n) / (FP32_PEAK_TFLOPS * 1e12))
+        st.init_zero()
+        st.apply_plan(p)
+        d2, dmax, ov, nrm = 0.0, 0.0, 0.0 + 0.0j, 0.0
+        step = 1 << 28
+        for i in range(0, 1 << n, step):
+            a = st.tensor[i:i + step].to(torch.complex128)
+            b = ref.tensor[i:i + step]
+            diff = (a - b).abs()
+            d2 += float((diff ** 2).sum().item())
+            dmax = max(dmax, float(diff.max().item()))
+            ov += complex(torch.vdot(b, a).item())
+            nrm += float((a.abs() ** 2).sum().item())
+        rig, typ = B.bound_for(p)
         res[name] = {"ms": round(ms, 2), "gate_applications_per_s": round(len(c) / (ms * 1e-3), 1),
                      "ops_mfma": s["ops_mfma"], "ops_dense": s["ops_dense"], "blocks": s["blocks"],
                      "swap_passes": s["swap_passes"], "flops_per_amp": s["flops_per_amp"],
-                     "state_error_bound_l2": bound}
-        log("complex64 32q %s: %.1f ms" % (name, ms))
+                     "roofline_frac": round(t_roof / (float(ms_steps.sum()) * 1e-3), 3),
+                     "hbm_gbs": round(passes * pass_bytes / (float(ms_steps.sum()) * 1e-3) / 1e9, 1),
+                     "fp32_tflops": round(s["flops_per_amp"] * (1 << n) / (float(ms_steps.sum()) * 1e-3) / 1e12, 2),
+                     "vs_complex128": {"l2": math.sqrt(d2), "max_abs": dmax, "one_minus_fidelity": 1 - abs(ov) ** 2 / nrm},
+                     "state_error_bound_l2": rig, "typical_estimate_l2": typ}
+        log("complex64 32q %s: %.1f ms, ||d||2 %.3e" % (name, ms, math.sqrt(d2)))
     res["speedup_mfma_vs_vector"] = round(res["vector"]["ms"] / res["mfma"]["ms"], 3)
-    del st
+    del st, ref
     return res
 
 
 def bench_qaoa(torch, I, qs):
     """512 MaxCut QAOA instances (3-regular, 10-20 qubits, p = 4, complex64):
-    one graph-captured persistent launch vs 512 sequential launches."""
+    one graph-captured persistent launch vs 512 sequential launches.  The
+    batch is bound by on-chip arithmetic and launch/queue latency, not HBM
+    (instances of <= 13 qubits never leave LDS): its roofline line is the
+    algorithmic FP32 rate (per layer and amplitude, the cost phase 6 flops and
+    each RX a dense 2x2 product, 16) against the FP32 peak."""
     insts = I.qaoa_batch(count=512, p=4, seed=512004)
     b = qs.QaoaBatch(insts, "c64")
     choice, tune_ms = b.autotune()
@@ -149,26 +219,127 @@ def bench_qaoa(torch, I, qs):
     seq = _ms(torch, lambda: b.run_sequential(), reps=3)
     err = b.error()
     gates = sum(len(q.circuit()) for q in insts)
+    flops = sum(float(1 << q.n) * len(q.gammas) * (6 + 16 * q.n) for q in insts)
     log("qaoa batch: %.2f ms batched, %.2f ms sequential" % (batched, seq))
     return {"workload": "512 QAOA MaxCut instances, random 3-regular graphs, 10-20 qubits, p=4, seed 512004, complex64",
             "batched_ms": round(batched, 3), "sequential_ms": round(seq, 3),
             "speedup_batched_vs_sequential": round(seq / batched, 2), "autotune_choice": choice,
-            "gate_applications_per_s_batched": round(gates / (batched * 1e-3), 1), "spin_error_flag": err}
+            "gate_applications_per_s_batched": round(gates / (batched * 1e-3), 1), "spin_error_flag": err,
+            "roofline": {"kernel": "k_qaoa", "bound": "alu", "algorithmic_flops": flops,
+                         "achieved_tflops": round(flops / (batched * 1e-3) / 1e12, 2), "peak_tflops": FP32_PEAK_TFLOPS,
+                         "frac": round(flops / (batched * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4)}}
 
 
-def bench_qft31(torch, I, qs):
-    """Context only: the 31-qubit QFT (496 gates, complex128, 32 GiB) that the paper times on one
-    A100 (3.6 s there, another machine); here from |0...0> through the fused, blocked path."""
-    c = I.qft(31)
-    p = qs.Plan(c, kmax=5)
-    st = qs.State(31, "c128")
-    ms = _ms(torch, lambda: (st.init_zero(), st.apply_plan(p)))
-    s = p.stats()
+TABLE1 = ("H", "U", "X", "CX", "CP", "SWAP", "RX", "RY", "RZ", "RZZ")
+
+
+def _table1_circuit(I, name, n, seed=71):
+    """One gate of the given type on every qubit (two-qubit gates on (q, q+1 mod n))."""
+    rng = np.random.default_rng(seed)
+    c = I.Circuit(n)
+    for q in range(n):
+        a = float(rng.uniform(0, 2 * math.pi))
+        if name == "H":
+            c.add("H", (q,), I.g_h())
+        elif name == "U":
+            c.add("U", (q,), I.g_u3(*(float(v) for v in rng.uniform(0, 2 * math.pi, 3))))
+        elif name == "X":
+            c.add("X", (q,), I.g_x())
+        elif name in ("RX", "RY", "RZ"):
+            c.add(name, (q,), {"RX": I.g_rx, "RY": I.g_ry, "RZ": I.g_rz}[name](a))
+        else:
+            m = {"CX": I.g_cx(), "CP": I.g_cp(a), "SWAP": I.g_swap(), "RZZ": I.g_rzz(a)}[name]
+            c.add(name, (q, (q + 1) % n), m)
+    return c
+
+
+def _touched_fraction(c):
+    """Fraction of the state a gate-by-gate pass of each gate reads and
+    writes: the rows of its matrix that are not unit diagonal rows (the
+    diagonal and permutation kinds touch only those; a control's 0 half is
+    such rows)."""
+    fr = []
+    for g in c.gates:
+        m = g.matrix
+        unit = sum(1 for r in range(m.shape[0]) if m[r, r] == 1 and np.count_nonzero(m[r]) == 1)
+        fr.append((m.shape[0] - unit) / m.shape[0])
+    return fr
+
+
+def bench_micro(torch, I, qs, amp_bytes=16.0):
+    """The paper's micro-benchmarks on MI355X: the H-gate qubit sweep (an H
+    on every qubit, 24..33 qubits) and the Table I gate set at 31 qubits (one
+    gate per qubit), gate by gate (one pass per gate, op kinds) vs fused and
+    blocked; time per gate and HBM roofline fraction per point."""
+    res = {"h_sweep": [], "table1_31q": []}
+    for n in range(24, 34):
+        c = _table1_circuit(I, "H", n)
+        st = qs.State(n, "c128")
+        p = qs.Plan(c, kmax=5)
+        s = p.stats()
+        pass_bytes = 2.0 * (1 << n) * amp_bytes
+        tb = _ms(torch, lambda: st.apply_plan(p))
+        tg = _ms(torch, lambda: st.apply_circuit_gbg(c), reps=1)
+        passes = s["blocks"] + s["swap_passes"]
+        res["h_sweep"].append({
+            "n": n, "gates": len(c), "fused_ms": round(tb, 3), "fused_ms_per_gate": round(tb / len(c), 4),
+            "fused_passes": passes, "fused_hbm_frac": round(passes * pass_bytes / (tb * 1e-3) / 1e9 / HBM_PEAK_GBS, 3),
+            "gbg_ms": round(tg, 3), "gbg_ms_per_gate": round(tg / len(c), 4),
+            "gbg_hbm_frac": round(len(c) * pass_bytes / (tg * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)})
+        del st
+        torch.cuda.empty_cache()
+        log("h sweep %d: fused %.2f ms, gbg %.2f ms" % (n, tb, tg))
+    n = 31
+    st = qs.State(n, "c128")
+    st.init_zero()
+    pass_bytes = 2.0 * (1 << n) * amp_bytes
+    for name in TABLE1:
+        c = _table1_circuit(I, name, n)
+        p = qs.Plan(c, kmax=5)
+        s = p.stats()
+        tb = _ms(torch, lambda: st.apply_plan(p))
+        tg = _ms(torch, lambda: st.apply_circuit_gbg(c), reps=1)
+        touched = sum(_touched_fraction(c))
+        passes = s["blocks"] + s["swap_passes"]
+        res["table1_31q"].append({
+            "gate": name, "gates": len(c), "fused_ms_per_gate": round(tb / len(c), 4), "fused_passes": passes,
+            "fused_hbm_frac": round(passes * pass_bytes / (tb * 1e-3) / 1e9 / HBM_PEAK_GBS, 3),
+            "gbg_ms_per_gate": round(tg / len(c), 4), "gbg_kind": qs.gate_class(c.gates[0].targets, c.gates[0].matrix)[0],
+            "gbg_touched_state_fraction": round(touched / len(c), 3),
+            "gbg_hbm_frac": round(touched * pass_bytes / (tg * 1e-3) / 1e9 / HBM_PEAK_GBS, 3),
+            "speedup_fused_vs_gbg": round(tg / tb, 2)})
+        log("table1 %s: fused %.3f ms/gate, gbg %.3f ms/gate" % (name, tb / len(c), tg / len(c)))
     del st
-    log("qft31: %.1f ms" % ms)
-    return {"workload": "QFT, 31 qubits, complex128 (496 gates: 31 H + 465 controlled phases)", "ms": round(ms, 2),
-            "blocks": s["blocks"], "swap_passes": s["swap_passes"],
-            "paper_a100_seconds": 3.6, "note": "the paper's number is on another machine (one A100): context, not a target"}
+    res["note"] = ("roofline fractions: algorithmic bytes (a full read+write pass per fused pass; the touched "
+                   "fraction of the state per gate-by-gate pass) / time / 8 TB/s")
+    return res
+
+
+def bench_headline31(torch, I, qs):
+    """The paper's headline circuits at 31 qubits (Table II): QFT (496 gates)
+    and QAOA p = 5 on the complete graph (2,511 gates), complex128, fused and
+    blocked, from |0...0>; the paper's single-A100 times are context only."""
+    out = {}
+    n = 31
+    pass_bytes = 2.0 * (1 << n) * 16
+    st = qs.State(n, "c128")
+    for key, c, paper_s in (("qft31", I.qft(n), 3.6), ("qaoa31_p5", I.qaoa_complete(n=n, p=5, seed=31005), 17.5)):
+        t0 = time.perf_counter()
+        p = qs.Plan(c, kmax=5)
+        plan_s = time.perf_counter() - t0
+        s = p.stats()
+        ms = _ms(torch, lambda: (st.init_zero(), st.apply_plan(p)))
+        ms_steps, kinds = st.apply_plan_timed(p)
+        passes = s["blocks"] + s["swap_passes"]
+        out[key] = {"gates": len(c), "ms": round(ms, 2), "gate_applications_per_s": round(len(c) / (ms * 1e-3), 1),
+                    "blocks": s["blocks"], "swap_passes": s["swap_passes"], "plan_seconds": round(plan_s, 3),
+                    "roofline": {"bound": "hbm", "achieved_gbs": round(passes * pass_bytes / (float(ms_steps.sum()) * 1e-3) / 1e9, 1),
+                                 "frac": round(passes * pass_bytes / (float(ms_steps.sum()) * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)},
+                    "paper_a100_seconds": paper_s}
+        log("%s: %.1f ms (%d passes)" % (key, ms, passes))
+    del st
+    out["note"] = "the paper's numbers are one A100 (another machine, raw circuits): context, not a target"
+    return out
 
 
 def bench_learned(torch, I, qs):
@@ -210,6 +381,7 @@ def main():
                     help="keep single-qubit gates whole (no phase * rotation * phase split)")
     ap.add_argument("--no-variants", action="store_true", help="skip the complex64 and batched-QAOA comparisons")
     ap.add_argument("--learned", action="store_true", help="also compare the learned planner at 33 qubits (128 GiB)")
+    ap.add_argument("--no-micro", action="store_true", help="skip the H-gate sweep and Table I gate benchmark")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no collectives); use --gpus 1", file=sys.stderr)
@@ -244,18 +416,20 @@ def main():
         step()
         log("warmup %d done" % i)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     t_wall = time.perf_counter()
-    e0.record(stream)
+    ev[0].record(stream)
     val = None
     for i in range(args.steps):
         val = step()
-    e1.record(stream)
+        ev[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
-    ms_total = e0.elapsed_time(e1)
+    ms_total = ev[0].elapsed_time(ev[-1])
     ms_step = ms_total / args.steps
-    log("timed %d steps: %.2f ms/step (wall %.2f s)" % (args.steps, ms_step, wall))
+    per_step = [ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)]
+    ms_median = float(np.median(per_step))
+    log("timed %d steps: %.2f ms/step mean, %.2f median (wall %.2f s)" % (args.steps, ms_step, ms_median, wall))
 
     # per-launch device times of the dominant kernel (the blocked pass)
     ms_steps, kinds = state.apply_plan_timed(plan)
@@ -296,6 +470,8 @@ def main():
         "unit": "gate-applications/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 3),
+        "ms_per_step_median": round(ms_median, 3),
+        "ms_per_step_min_max": [round(min(per_step), 3), round(max(per_step), 3)],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic (seeded random circuit, explicit FP64 gate matrices)",
         "config": {"workload": "random U3 + CZ(random perfect matching), %d qubits, depth %d, seed %d, "
@@ -337,7 +513,10 @@ def main():
         torch.cuda.empty_cache()
         out["qaoa_batch"] = bench_qaoa(torch, I, qs)
         torch.cuda.empty_cache()
-        out["context_qft31"] = bench_qft31(torch, I, qs)
+        out["headline_31q"] = bench_headline31(torch, I, qs)
+        torch.cuda.empty_cache()
+    if not args.no_micro:
+        out["micro"] = bench_micro(torch, I, qs)
         torch.cuda.empty_cache()
     if args.learned:
         out["learned_planner_33q"] = bench_learned(torch, I, qs)
@@ -346,6 +525,8 @@ def main():
     if not args.no_cpu:
         log("cpu oracle baseline (bounded sample)")
         out["cpu_baseline"] = cpu_baseline(circ, max_gates=64, budget_s=args.cpu_budget)
+        out["cpu_baseline"]["cpu_model"] = cpu_model()
+        out["cpu_baseline"]["c1_16q_full_circuit"] = cpu_c1_full()
 
     print(json.dumps(out), flush=True)
 

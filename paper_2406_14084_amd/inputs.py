@@ -271,6 +271,32 @@ def qft(n):
     return c
 
 
+def qaoa_complete(n=31, p=5, seed=31005):
+    """QAOA on the complete graph with the paper's Table II gate count: H on
+    every qubit, then per layer l RZZ(gamma_l) on every pair (j, k), j < k
+    (ascending j, then k), and RX(beta_l) on every qubit: n + p (n(n-1)/2 + n)
+    gates (2,511 at n = 31, p = 5).  gamma_l, beta_l ~ U[0, 2pi), drawn gamma
+    then beta per layer."""
+    rng = np.random.default_rng(seed)
+    c = Circuit(n)
+    for q in range(n):
+        c.add("H", (q,), g_h())
+    for _ in range(p):
+        gamma, beta = (float(v) for v in rng.uniform(0.0, 2 * math.pi, size=2))
+        for j in range(n):
+            for k in range(j + 1, n):
+                c.add("RZZ", (j, k), g_rzz(gamma))
+        for q in range(n):
+            c.add("RX", (q,), g_rx(beta))
+    return c
+
+
+def qaoa_complete_angles(p=5, seed=31005):
+    """The (gamma_l, beta_l) that qaoa_complete draws."""
+    rng = np.random.default_rng(seed)
+    return [tuple(float(v) for v in rng.uniform(0.0, 2 * math.pi, size=2)) for _ in range(p)]
+
+
 def ghz(n):
     """H on qubit 0, then CX(0 -> i) for i = 1..n-1."""
     c = Circuit(n)

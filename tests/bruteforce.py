@@ -12,6 +12,8 @@ from __future__ import annotations
 import itertools
 import math
 
+import math
+
 import numpy as np
 
 _I2 = np.eye(2, dtype=np.complex128)
@@ -116,3 +118,24 @@ def qaoa_bruteforce(n, edges, gammas, betas):
 def all_pauli_masks(n):
     for x, z in itertools.product(range(1 << n), repeat=2):
         yield x, z
+
+
+def dicke_amplitudes(n, angles):
+    """Amplitude of a basis state of Hamming weight w, for w = 0..n, after H on
+    every qubit and p layers of (RZZ(gamma) on every pair, RX(beta) on every
+    qubit), computed in the (n+1)-dimensional symmetric (Dicke) subspace:
+    H^n gives c_w = sqrt(C(n, w)) 2^{-n/2}; the RZZ layer multiplies c_w by
+    exp(-i gamma/2 * ((n - 2w)^2 - n) / 2); the RX layer is exp(-i beta J_x)
+    with <D_{w+1}|J_x|D_w> = sqrt((w + 1)(n - w)) / 2; the amplitude is
+    c_w / sqrt(C(n, w))."""
+    w = np.arange(n + 1)
+    binom = np.array([math.comb(n, int(k)) for k in w], dtype=np.float64)
+    c = np.sqrt(binom) * 2.0 ** (-n / 2) + 0j
+    off = 0.5 * np.sqrt((w[:-1] + 1.0) * (n - w[:-1]))
+    Jx = np.diag(off, 1) + np.diag(off, -1)
+    lam, V = np.linalg.eigh(Jx)
+    S = n - 2 * w
+    for gamma, beta in angles:
+        c = c * np.exp(-0.5j * gamma * (S * S - n) / 2.0)
+        c = V @ (np.exp(-1j * beta * lam) * (V.T @ c))
+    return c / np.sqrt(binom)

@@ -207,10 +207,20 @@ def check_qaoa(L):
         assert abs(v - bf.qaoa_bruteforce(n, edges, g, b)) <= 1e-12
 
 
+def check_qaoa_complete_closed_form(L):
+    """H^n then RZZ on every pair and RX on every qubit keep the state
+    symmetric: the oracle equals the symmetric-subspace closed form."""
+    for n, p, seed in ((6, 2, 3), (9, 3, 7)):
+        psi = sim.run(I.qaoa_complete(n=n, p=p, seed=seed), L)
+        f = bf.dicke_amplitudes(n, I.qaoa_complete_angles(p=p, seed=seed))
+        w = np.array([bin(i).count("1") for i in range(1 << n)])
+        assert np.max(np.abs(psi - f[w])) <= 1e-13, n
+
+
 ALL_CHECKS = [check_kron_bruteforce, check_h_all, check_ghz, check_x_all, check_cnot_orientation,
               check_rotation_expectations, check_norm_and_inverse, check_qft_closed_form,
               check_swap_tensor, check_pauli_bruteforce, check_probs, check_worked_example_d4,
-              check_qaoa]
+              check_qaoa, check_qaoa_complete_closed_form]
 
 
 @pytest.mark.parametrize("check", ALL_CHECKS, ids=lambda f: f.__name__)
