@@ -260,6 +260,17 @@ QS_API qs_status qs_probs(qs_state *st, double *out_dev);
  * in a fixed order.  Synchronises the stream. */
 QS_API qs_status qs_expect(qs_state *st, int nterms, const qs_pauli *terms, double *out_host);
 
+/* For callers that cannot allocate device memory (work under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * value as qs_expect, but the terms and the per-workgroup partial sums go to
+ * a fixed array inside the library (about 1 MiB per GPU, held until the
+ * process ends) instead of the handle's workspace, and the partials are
+ * summed on the device in the same fixed order.  At most 64 terms per call
+ * (QS_EINVAL beyond).  Calls no hipMalloc/hipFree.  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (other threads,
+ * other streams) race.  Synchronises the stream. */
+QS_API qs_status qs_expect_noalloc(qs_state *st, int nterms, const qs_pauli *terms, double *out_host);
+
 /* Copy amplitudes [first, first + count) of the state (2^n of them,
  * interleaved re/im at the state's precision, 16 or 8 bytes each) to host
  * memory host_out, in canonical qubit order.  Paper: Alg. 3's output, the

@@ -86,6 +86,7 @@ SIGNATURES = {
                                   C.POINTER(C.c_int), C.POINTER(C.c_double), C.c_size_t, C.POINTER(C.c_size_t)]),
     "qs_probs": (C.c_int, [_P, _P]),
     "qs_expect": (C.c_int, [_P, C.c_int, C.POINTER(Pauli_C), C.POINTER(C.c_double)]),
+    "qs_expect_noalloc": (C.c_int, [_P, C.c_int, C.POINTER(Pauli_C), C.POINTER(C.c_double)]),
     "qs_batch_qaoa_create": (C.c_int, [C.c_int, C.POINTER(QaoaInst_C), C.c_int, _P, _P, C.c_size_t, C.POINTER(_P)]),
     "qs_batch_qaoa_workspace_size": (C.c_int, [C.c_int, C.POINTER(QaoaInst_C), C.c_int, C.POINTER(C.c_size_t)]),
     "qs_batch_qaoa_run": (C.c_int, [_P, _P, C.c_int]),
