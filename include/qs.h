@@ -123,6 +123,7 @@ typedef struct {
     double predicted_heuristic_ms; /* learned planner: predicted time of the heuristic plan, else -1 */
     int ops_mfma;         /* dense ops (counted in ops_dense too) that run on matrix cores */
     int ops_rot;          /* single-qubit real rotations applied as shears (one per bit of each rotation op) */
+    int ops_perm;         /* permutation ops (X, CX, CCX, SWAP on register bits): data movement, no arithmetic */
 } qs_plan_stats;
 
 /* ---- state handles ------------------------------------------------------ */

@@ -196,6 +196,69 @@ __device__ __forceinline__ void rot_dispatch(int mask, V (&v)[1 << R], P M)
 }
 #undef QS_ROT_CASE
 
+// Permutation ops: no arithmetic, the compile-time register indices move.
+// Multi-controlled X: flip register bit T of every register whose CTRL bits are
+// all set (X: CTRL = 0, CX: one control, CCX: two).
+template <int R, int T, int CTRL, typename V>
+__device__ __forceinline__ void apply_mcx(V (&v)[1 << R])
+{
+#pragma unroll
+    for (int m = 0; m < (1 << R); ++m) {
+        if ((m & CTRL) != CTRL || ((m >> T) & 1)) continue;
+        const V t = v[m];
+        v[m] = v[m | (1 << T)];
+        v[m | (1 << T)] = t;
+    }
+}
+
+// SWAP: exchange register bits A and B.
+template <int R, int A, int B, typename V>
+__device__ __forceinline__ void apply_swapr(V (&v)[1 << R])
+{
+#pragma unroll
+    for (int m = 0; m < (1 << R); ++m) {
+        if (((m >> A) & 1) != 1 || ((m >> B) & 1) != 0) continue;
+        const int m2 = (m & ~(1 << A)) | (1 << B);
+        const V t = v[m];
+        v[m] = v[m2];
+        v[m2] = t;
+    }
+}
+
+// variant = T | CTRL << 3 for MCX, A | B << 3 for SWAPR; values the host never
+// encodes (checked when the program is built) are unreachable
+#define QS_PERM_CASE(VV)                                                                            \
+    case VV:                                                                                        \
+        if constexpr (SW) {                                                                         \
+            if constexpr (((VV) & 7) < ((VV) >> 3) && ((VV) >> 3) < R)                              \
+                apply_swapr<R, ((VV) & 7), (((VV) >> 3) < R ? ((VV) >> 3) : 0), V>(v);              \
+            else                                                                                    \
+                __builtin_unreachable();                                                            \
+        } else {                                                                                    \
+            if constexpr (((VV) & 7) < R && ((VV) >> 3) < (1 << R) && !((((VV) >> 3) >> ((VV) & 7)) & 1)) \
+                apply_mcx<R, (((VV) & 7) < R ? ((VV) & 7) : 0), ((VV) >> 3), V>(v);                 \
+            else                                                                                    \
+                __builtin_unreachable();                                                            \
+        }                                                                                           \
+        break;
+#define QS_PERM_C4(X) QS_PERM_CASE(X) QS_PERM_CASE(X + 1) QS_PERM_CASE(X + 2) QS_PERM_CASE(X + 3)
+#define QS_PERM_C16(X) QS_PERM_C4(X) QS_PERM_C4(X + 4) QS_PERM_C4(X + 8) QS_PERM_C4(X + 12)
+#define QS_PERM_C64(X) QS_PERM_C16(X) QS_PERM_C16(X + 16) QS_PERM_C16(X + 32) QS_PERM_C16(X + 48)
+
+template <int R, bool SW, typename V>
+__device__ __forceinline__ void perm_dispatch(int var, V (&v)[1 << R])
+{
+    switch (var) {
+        QS_PERM_C64(0) QS_PERM_C64(64) QS_PERM_C64(128) QS_PERM_C64(192)
+    default:
+        __builtin_unreachable();
+    }
+}
+#undef QS_PERM_C64
+#undef QS_PERM_C16
+#undef QS_PERM_C4
+#undef QS_PERM_CASE
+
 // bits of v selected by MASK, packed to the low end (compile time)
 template <int MASK>
 __device__ __forceinline__ constexpr int pext_c(int v)
@@ -569,6 +632,10 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
                 if (kind == OP_MULTI1) {
                     if constexpr (KMAX > 0) multi1_dispatch<R, F, V, const CF *>(variant, v, M);
                     else __builtin_unreachable();
+                } else if (kind == OP_MCX) {
+                    perm_dispatch<R, false, V>(variant, v);
+                } else if (kind == OP_SWAPR) {
+                    perm_dispatch<R, true, V>(variant, v);
                 } else if (kind == OP_ROT) {
                     rot_dispatch<R, F, V, const CF *>(variant, v, M);
                 } else if (kind == OP_DENSE) {
@@ -599,10 +666,23 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
                     }
                 } else {   // this lane's row of the op's table (LDS, or device memory)
                     const uint32_t row = pext_u32(tid, (uint32_t)op[1]);
-                    auto apply_row = [&](const V *__restrict__ E) __attribute__((always_inline)) {
+                    // the row holds entries over the op's register bits only: register m
+                    // takes entry pext(m, rmask); per register bit j the (uniform) byte
+                    // stride of the entry index
+                    const uint32_t rm = (uint32_t)variant >> 1;
+                    const uint32_t kr = __builtin_popcount(rm);
+                    uint32_t stride[R];
+#pragma unroll
+                    for (int j = 0; j < R; ++j)
+                        stride[j] = ((rm >> j) & 1u) ? (uint32_t)sizeof(V) << __builtin_popcount(rm & ((1u << j) - 1u)) : 0u;
+                    auto apply_row = [&](const unsigned char *__restrict__ E) __attribute__((always_inline)) {
 #pragma unroll
                         for (int m = 0; m < NR; ++m) {
-                            const V e = E[m];
+                            uint32_t off = 0;
+#pragma unroll
+                            for (int j = 0; j < R; ++j)
+                                if ((m >> j) & 1) off += stride[j];
+                            const V e = *reinterpret_cast<const V *>(E + off);
                             v[m] = cmul<F, V>(e.x, e.y, v[m]);
                             // keep at most four table reads in flight (register pressure)
                             if ((m & 3) == 3) __builtin_amdgcn_sched_barrier(0);
@@ -610,11 +690,12 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
                     };
                     // two separate paths, so the LDS one is plain LDS reads (a pointer that
                     // may be either would become flat loads, waited on with the memory counter)
-                    if (variant)
-                        apply_row(reinterpret_cast<const V *>(mats + ((int64_t)(uint32_t)op[2] | ((int64_t)op[3] << 32))) +
-                                  (size_t)row * NR);
+                    if (variant & 1)
+                        apply_row(reinterpret_cast<const unsigned char *>(
+                                      mats + ((int64_t)(uint32_t)op[2] | ((int64_t)op[3] << 32))) +
+                                  ((size_t)row * sizeof(V) << kr));
                     else
-                        apply_row(reinterpret_cast<const V *>(ltab + op[3]) + (size_t)row * NR);
+                        apply_row(reinterpret_cast<const unsigned char *>(ltab + op[3]) + ((size_t)row * sizeof(V) << kr));
                 }
             };
             if constexpr (KMAX == 0) {

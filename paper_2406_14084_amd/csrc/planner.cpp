@@ -150,6 +150,9 @@ std::vector<char> choose_chunk(Blocker &B, const std::vector<int> &rem, const st
 struct SetOp {
     bool diag = false;
     bool rot = false;            // real plane rotations (one per bit of mask); m = their dense matrix when one bit
+    int perm = 0;                // permutation without arithmetic: 1 = multi-controlled X on bit ptarget (the
+                                 // other bits of mask control), 2 = SWAP of the two bits of mask; m = its matrix
+    int ptarget = -1;
     bool pin = false;            // diagonal split off a single-qubit gate: runs only while its bits are in registers
     uint32_t mask = 0;           // local chunk bits
     std::vector<cplx> m;         // dense: d*d; diag: d
@@ -245,6 +248,8 @@ double op_cost(bool diag, int k, bool mfma = false)
 }
 // a real rotation by three shears: three FMAs per amplitude (real and imaginary parts)
 constexpr double kRotCost = 3.0;
+// a permutation op: register moves only
+constexpr double kPermCost = 0.25;
 
 // Single-qubit gate as diag(p) * Rot(theta) * diag(q), Rot = [[c, -s], [s, c]] with
 // c = cos theta, s = sin theta, theta in [0, pi/2] (the phases absorb every sign).
@@ -279,6 +284,30 @@ bool split_rotation(const std::vector<cplx> &u, cplx *pre, cplx *post, double *a
     return true;
 }
 
+// A dense set op whose matrix is exactly a multi-controlled X (X, CX, CCX: flip one
+// bit where every other bit of the op is 1) or a SWAP of its two bits becomes a
+// permutation op: the kernel moves registers and does no arithmetic.
+void classify_perm(SetOp *s)
+{
+    const int k = popc(s->mask), d = 1 << k;
+    if (k > 3) return;
+    auto matches = [&](auto f) {
+        for (int r = 0; r < d; ++r)
+            for (int c = 0; c < d; ++c)
+                if (s->m[(size_t)r * d + c] != cplx(f(c) == r ? 1.0 : 0.0, 0.0)) return false;
+        return true;
+    };
+    for (int t = 0; t < k; ++t) {
+        const int ctrl = (d - 1) & ~(1 << t);
+        if (matches([&](int c) { return (c & ctrl) == ctrl ? c ^ (1 << t) : c; })) {
+            s->perm = 1;
+            s->ptarget = __builtin_ctz(pdep(1 << t, s->mask));
+            return;
+        }
+    }
+    if (k == 2 && matches([](int c) { return ((c & 1) << 1) | ((c >> 1) & 1); })) s->perm = 2;
+}
+
 // Convert a circuit gate to a set op over local bits (loc[j] = local bit of t[j]).
 SetOp gate_to_setop(const GateIn &G, const int *loc, int gid)
 {
@@ -303,6 +332,7 @@ SetOp gate_to_setop(const GateIn &G, const int *loc, int gid)
         s.m.assign((size_t)d * d, cplx(0, 0));
         for (int r = 0; r < d; ++r)
             for (int c = 0; c < d; ++c) s.m[(size_t)map[r] * d + map[c]] = G.m[(size_t)r * d + c];
+        classify_perm(&s);
     }
     return s;
 }
@@ -435,20 +465,49 @@ struct PhaseSched {
     //    commute), as long as the merged diagonal has at most kMaxDiagBits bits.
     // Order of the fused ops of one phase, by list scheduling over their
     // dependences (ops sharing a bit depend on each other unless both are
-    // diagonal): whenever diagonals are ready they go out first, merged into as
-    // few ops as kMaxDiagBits and the rules below allow (a +-1 diagonal stays a
-    // free sign flip unless it joins a register-bit table); then all ready
-    // rotations as one op; otherwise the earliest ready op.  A layer of split
+    // diagonal; a diagonal moves ahead of permutations, conjugated): whenever
+    // diagonals are ready they go out first, merged into as few ops as
+    // kMaxDiagBits and the rules below allow (a +-1 diagonal stays a free sign
+    // flip unless it joins a register-bit table); then all ready permutations;
+    // then all ready rotations as one op; otherwise the earliest ready op.  A layer of split
     // single-qubit gates thus becomes one diagonal, one rotation op over all its
     // register bits, and one diagonal shared with the next layer.
-    std::vector<SetOp> reschedule(const std::vector<SetOp> &ops, uint32_t R) const
+    // A diagonal D after a permutation P equals P then D' before it, D'(x) = D(P x):
+    // diagonals move ahead of permutation ops (their entries permuted, their bit set
+    // growing by the permutation's bits), so a layer's phases merge across CX gates.
+    static SetOp conjugate_through(const SetOp &d, const SetOp &pm)
     {
+        if (!(d.mask & pm.mask)) return d;
+        SetOp r = d;
+        r.mask = d.mask | pm.mask;
+        const int k = popc(r.mask);
+        r.m.assign((size_t)1 << k, cplx(0, 0));
+        const uint32_t ctrl = pm.perm == 1 ? (pm.mask & ~(1u << pm.ptarget)) : 0;
+        for (int u = 0; u < (1 << k); ++u) {
+            uint32_t x = pdep(u, r.mask), y = x;
+            if (pm.perm == 1) {
+                if ((x & ctrl) == ctrl) y ^= 1u << pm.ptarget;
+            } else {
+                const int a = __builtin_ctz(pm.mask), b = 31 - __builtin_clz(pm.mask);
+                const uint32_t ba = (x >> a) & 1, bb = (x >> b) & 1;
+                y = (x & ~((1u << a) | (1u << b))) | (ba << b) | (bb << a);
+            }
+            r.m[u] = d.m[pext(y, d.mask)];
+        }
+        return r;
+    }
+
+    std::vector<SetOp> reschedule(const std::vector<SetOp> &ops_in, uint32_t R) const
+    {
+        std::vector<SetOp> ops = ops_in;
         const size_t n = ops.size();
         std::vector<std::vector<int>> succ(n);
         std::vector<int> pending(n, 0);     // undone predecessors
+        // a diagonal does not wait for permutation ops: it is conjugated through every one
+        // still pending before it when it goes out (see diag_ahead)
         for (size_t j = 0; j < n; ++j)
             for (size_t i = 0; i < j; ++i)
-                if ((ops[i].mask & ops[j].mask) && !(ops[i].diag && ops[j].diag)) {
+                if ((ops[i].mask & ops[j].mask) && !(ops[i].diag && ops[j].diag) && !(ops[i].perm && ops[j].diag)) {
                     succ[i].push_back((int)j);
                     ++pending[j];
                 }
@@ -466,14 +525,41 @@ struct PhaseSched {
                 for (int j : succ[i]) --pending[j];
             finished.clear();
             std::vector<int> ready;
+            // a diagonal j whose permutation predecessors are pending moves ahead of every
+            // pending op before it, crossing them from right to left: a permutation
+            // conjugates it (its bit set grows), any other non-diagonal op must not share a
+            // bit with it at that point; the result stays within kMaxDiagBits bits
+            auto diag_ahead = [&](int j, SetOp *outp) {
+                SetOp d = ops[j];
+                for (int i = j - 1; i >= 0; --i) {
+                    if (done[i] || ops[i].diag) continue;
+                    if (ops[i].perm) d = conjugate_through(d, ops[i]);
+                    else if (ops[i].mask & d.mask) return false;
+                }
+                if (popc(d.mask) > kMaxDiagBits) return false;
+                if (outp) *outp = d;
+                return true;
+            };
             for (size_t j = 0; j < n; ++j)
-                if (!done[j] && pending[j] == 0) ready.push_back((int)j);
-            std::vector<int> rd, rr;
+                if (!done[j] && pending[j] == 0 && (!ops[j].diag || diag_ahead((int)j, nullptr))) ready.push_back((int)j);
+            for (int j : ready)
+                if (ops[j].diag) diag_ahead(j, &ops[j]);
+            std::vector<int> rd, rr, rp;
             for (int j : ready) {
                 if (ops[j].diag) rd.push_back(j);
                 else if (ops[j].rot) rr.push_back(j);
+                else if (ops[j].perm) rp.push_back(j);
             }
-            if (!rd.empty()) {
+            if (rd.empty() && !rp.empty()) {
+                // ready permutations (mutually independent) before rotations: they cost
+                // nothing and let the rotations of a layer go out together
+                for (int j : rp) {
+                    out.push_back(ops[j]);
+                    done[j] = 1;
+                    finished.push_back(j);
+                    --left;
+                }
+            } else if (!rd.empty()) {
                 std::vector<SetOp> groups;
                 for (int j : rd) {
                     const SetOp &o = ops[j];
@@ -541,11 +627,16 @@ struct PhaseSched {
                 SetOp &f = out[F];
                 uint32_t U = f.mask | o.mask;
                 int kU = popc(U);
-                auto cost = [&](const SetOp &x) { return x.rot ? kRotCost : op_cost(x.diag, popc(x.mask), mfma); };
+                auto cost = [&](const SetOp &x) {
+                    return x.rot ? kRotCost : x.perm ? kPermCost : op_cost(x.diag, popc(x.mask), mfma);
+                };
                 double before = cost(f) + cost(o);
                 bool ok;
                 // split-off phases merge later, in reschedule, once a whole layer is ready
                 if (f.diag && o.diag) ok = kU <= kMaxDiagBits && !f.pin && !o.pin;
+                // a permutation stays free: it merges only into a dense op that covers its bits,
+                // and a dense op only into it when the result is no wider than that dense op
+                else if ((f.perm && (o.diag || o.rot || o.perm)) || (o.perm && (f.diag || f.rot || f.perm))) ok = false;
                 else if (!f.diag && o.diag) ok = !f.rot && (o.mask & ~f.mask) == 0;
                 else if (f.diag && o.rot) ok = false;        // keep the split: the phase stays a cheap diagonal
                 else ok = (U & ~R) == 0 && kU <= kmax && op_cost(false, kU, mfma) <= before;
@@ -586,6 +677,18 @@ Op to_kernel_op(const SetOp &s, const Layout &lay, int r)
     op.gate_ids = s.gate_ids;
     op.k = popc(s.mask);
     op.m = s.m;
+    if (s.perm) {
+        op.kind = s.perm == 1 ? OP_MCX : OP_SWAPR;
+        int mask = 0;
+        for (int j = 0; j < r; ++j) {
+            if (s.mask >> lay.R[j] & 1) mask |= 1 << j;
+            if (s.perm == 1 && lay.R[j] == s.ptarget) op.ptarget = j;
+        }
+        op.regmask = mask;
+        if (popc((uint32_t)mask) != op.k || (s.perm == 1 && op.ptarget < 0))
+            throw std::logic_error("permutation op on a bit outside the phase's registers");
+        return op;
+    }
     if (s.rot) {
         // coefficients (a, b) per register bit, ascending register index
         op.kind = OP_ROT;
@@ -915,7 +1018,10 @@ qs_status build_plan(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan 
             cplx pre[2], post[2];
             double ra, rb;
             std::vector<cplx> rm;
-            if (split && G.k == 1 && !G.diag && split_rotation(G.m, pre, post, &ra, &rb, &rm)) {
+            // (an X stays a permutation op: register moves instead of a rotation)
+            const bool is_x = G.k == 1 && G.m[0] == cplx(0, 0) && G.m[1] == cplx(1, 0) && G.m[2] == cplx(1, 0) &&
+                              G.m[3] == cplx(0, 0);
+            if (split && G.k == 1 && !G.diag && !is_x && split_rotation(G.m, pre, post, &ra, &rb, &rm)) {
                 // phase, rotation, phase: the phases merge with neighbouring diagonals
                 SetOp d0, rt, d1;
                 d0.diag = d1.diag = true;
@@ -1218,6 +1324,7 @@ qs_status build_plan(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan 
                 if (op.kind == OP_DIAG) { ++s.ops_diag; s.flops_per_amp += 6.0; }
                 else if (op.kind == OP_MULTI1) { s.ops_dense[1] += op.k; s.flops_per_amp += 16.0 * op.k; }
                 else if (op.kind == OP_ROT) { s.ops_rot += op.k; s.flops_per_amp += 6.0 * op.k; }
+                else if (op.kind == OP_MCX || op.kind == OP_SWAPR) ++s.ops_perm;
                 else {
                     ++s.ops_dense[op.k];
                     s.flops_per_amp += 8.0 * (double)(1 << op.k);
@@ -1331,6 +1438,8 @@ static void check_program(const Plan &p)
                 case OP_DENSE: ok = var > 0 && var < NR && __builtin_popcount(var) <= kw; break;
                 case OP_MULTI1: ok = kw >= 1 && var > 0 && var < NR; break;
                 case OP_ROT: ok = var > 0 && var < NR; break;
+                case OP_MCX: ok = (var & 7) < r && (var >> 3) < NR && !(((var >> 3) >> (var & 7)) & 1); break;
+                case OP_SWAPR: ok = (var & 7) < (var >> 3) && (var >> 3) < r; break;
                 case OP_MFMA:
                     ok = bm && r == 5 && (var == 15 || var == 23 || var == 27 || var == 29 || var == 30 || var == 31);
                     break;
@@ -1404,8 +1513,10 @@ void encode_plan(Plan *p)
         for (int b = 0; b < C; ++b) w.push_back(blk.P_out[b]);
         std::vector<int32_t> tab;   // per-lane data of diagonal ops, staged in LDS by the kernel
         const bool c64 = (p->dtype == QS_C64);
-        // LDS left beside the chunk's exchange buffer (words); larger tables go to device memory
-        const size_t tab_cap = (160u * 1024u - ((size_t)(c64 ? 8 : 16) << C)) / 4;
+        // Per-lane tables staged in LDS are capped at 16 KiB so that the workgroups per CU
+        // stay what the exchange buffer allows (half buffer: three, whole buffer: two);
+        // larger tables are read from device memory (L2) instead.
+        const size_t tab_cap = std::min<size_t>(4096, (160u * 1024u - ((size_t)(c64 ? 8 : 16) << C)) / 4);
         for (size_t ph = 0; ph < blk.phases.size(); ++ph) {
             const Phase &P = blk.phases[ph];
             uint64_t swz = (ph > 0) ? choose_swizzle(blk.phases[ph - 1].lay, P.lay, C, r) : 0;
@@ -1498,6 +1609,21 @@ void encode_plan(Plan *p)
                     w.push_back(0);
                     continue;
                 }
+                if (op.kind == OP_MCX || op.kind == OP_SWAPR) {
+                    int var;
+                    if (op.kind == OP_MCX) {
+                        var = op.ptarget | ((op.regmask & ~(1 << op.ptarget)) << 3);
+                    } else {
+                        const int a = __builtin_ctz((unsigned)op.regmask);
+                        const int b = 31 - __builtin_clz((unsigned)op.regmask);
+                        var = a | (b << 3);
+                    }
+                    w.push_back(op.kind | (var << 8) | (op.k << 16));
+                    w.push_back(0);
+                    w.push_back(0);
+                    w.push_back(0);
+                    continue;
+                }
                 if (op.kind == OP_DENSE || op.kind == OP_MULTI1 || op.kind == OP_ROT) {
                     // rotations: (a, b) per register bit in the real and imaginary slots
                     for (const cplx &z : op.m) { p->h_mats.push_back(z.real()); p->h_mats.push_back(z.imag()); }
@@ -1565,29 +1691,41 @@ void encode_plan(Plan *p)
                     w.push_back(0);
                     continue;
                 }
-                const size_t row_words = (size_t)NR * (c64 ? 2 : 4);
+                // a row holds the entries over the op's register bits only (rmask, register
+                // positions): 2^kr of them, entry e for every register m with pext(m, rmask) = e
+                uint32_t rmask = 0;
+                for (int j = 0; j < r; ++j)
+                    if (opmask >> P.lay.R[j] & 1) rmask |= 1u << j;
+                const int kr = popc(rmask), ne = 1 << kr;
+                auto reg_of = [&](int e) {
+                    int m = 0, i = 0;
+                    for (int j = 0; j < r; ++j)
+                        if (rmask >> j & 1) { m |= ((e >> i) & 1) << j; ++i; }
+                    return m;
+                };
+                const size_t row_words = (size_t)ne * (c64 ? 2 : 4);
                 if (global_tab || ((tab.size() + 3) & ~(size_t)3) + (size_t)rows * row_words > tab_cap) {
-                    // table in device memory (variant 1): rows of 2^r entries, interleaved re/im
+                    // table in device memory (variant bit 0): rows of 2^kr entries, interleaved re/im
                     for (int row = 0; row < rows; ++row)
-                        for (int m = 0; m < NR; ++m) {
-                            cplx z = entry(row, m);
+                        for (int e = 0; e < ne; ++e) {
+                            cplx z = entry(row, reg_of(e));
                             p->h_mats.push_back(z.real());
                             p->h_mats.push_back(z.imag());
                         }
-                    w.push_back(OP_DIAG_ROW | (1 << 8) | (op.k << 16));
+                    w.push_back(OP_DIAG_ROW | ((1 | (int)(rmask << 1)) << 8) | (op.k << 16));
                     w.push_back((int32_t)tmask);
                     w.push_back((int32_t)(uint32_t)(moff & 0xffffffff));
                     w.push_back((int32_t)(uint32_t)(moff >> 32));
                     continue;
                 }
                 while (tab.size() % 4) tab.push_back(0);     // 16-byte aligned rows
-                w.push_back(OP_DIAG_ROW | (op.k << 16));
+                w.push_back(OP_DIAG_ROW | ((int)(rmask << 1) << 8) | (op.k << 16));
                 w.push_back((int32_t)tmask);
                 w.push_back(0);
                 w.push_back((int32_t)tab.size());
                 for (int row = 0; row < rows; ++row)
-                    for (int m = 0; m < NR; ++m) {
-                        cplx z = entry(row, m);
+                    for (int e = 0; e < ne; ++e) {
+                        cplx z = entry(row, reg_of(e));
                         if (c64) {
                             float f[2] = {(float)z.real(), (float)z.imag()};
                             int32_t u[2];
@@ -1648,7 +1786,8 @@ std::string dump_plan(const Plan &p)
                     for (int j = 0; j < op.k; ++j) os << " " << op.tl[j];
                     os << " " << op.m[0].real() << " " << op.m[0].imag();
                 } else {
-                    os << (op.kind == OP_MULTI1 ? "M" : op.kind == OP_ROT ? "R" : "U") << op.k;
+                    os << (op.kind == OP_MULTI1 ? "M" : op.kind == OP_ROT ? "R" : op.kind == OP_MCX ? "X"
+                           : op.kind == OP_SWAPR ? "S" : "U") << op.k;
                     for (int j = 0; j < p.r; ++j)
                         if (op.regmask >> j & 1) os << " " << ph.lay.R[j];
                 }

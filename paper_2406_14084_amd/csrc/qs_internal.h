@@ -35,8 +35,11 @@ enum OpKind {
     OP_SIGN_ROW = 5,   //   entries all +-1 with thread bits: one such mask per row
     OP_MULTI1 = 6,     // one 2x2 gate on each register bit of regmask (they commute), ascending bit order
     OP_MFMA = 7,       // encoding of a complex64 dense op of k >= 4 register bits run on matrix cores
-    OP_ROT = 8         // a real plane rotation on each register bit of regmask, as three shears
+    OP_ROT = 8,        // a real plane rotation on each register bit of regmask, as three shears
                        // x0 += a x1, x1 += b x0, x0 += a x1 (coefficients (a, b) per bit, ascending)
+    OP_MCX = 9,        // permutation, no arithmetic: flip register bit ptarget of every register whose
+                       // bits in regmask & ~(1 << ptarget) (the controls) are all set (X, CX, CCX)
+    OP_SWAPR = 10      // permutation, no arithmetic: exchange the two register bits of regmask (SWAP)
 };
 
 struct Op {
@@ -45,6 +48,7 @@ struct Op {
     //        matrix index bit i <-> the i-th lowest set bit of the mask.
     // Diag:  local chunk bits tl[0..k-1] ascending; table index bit i <-> tl[i].
     int regmask = 0;
+    int ptarget = -1;             // OP_MCX: register position of the flipped bit
     int k = 0;
     int tl[kMaxDiagBits] = {0};
     std::vector<cplx> m;          // dense: (2^k)^2 row-major; diag: 2^k
@@ -128,14 +132,19 @@ qs_status build_plan_search(const qs_circuit *c, int kmax, const qs_plan_opts *o
 //       DENSE   : variant = register mask; w1,w2 = matrix offset (scalars, lo/hi)
 //       MULTI1  : variant = register mask; w1,w2 = offset of one 2x2 matrix per set bit, ascending
 //       DIAG_REG: w1,w2 = offset of 2^r entries (register order)
-//       DIAG_ROW: w1 = tmask (thread-index bits of the row); variant 0: w3 = word offset in the
-//                 table of 2^kt rows of 2^r entries (complex128: 4 words each, complex64: 2);
-//                 variant 1 (table too large for LDS): w2,w3 = offset of the rows in the matrices
+//       DIAG_ROW: w1 = tmask (thread-index bits of the row); variant bits 1-5 = rmask, the
+//                 register positions the op touches: a row holds 2^kr entries (kr = popcount
+//                 rmask), register m takes entry pext(m, rmask); variant bit 0 clear: w3 = word
+//                 offset in the LDS table of 2^kt rows (complex128: 4 words per entry,
+//                 complex64: 2); bit 0 set (table too large for LDS): w2,w3 = offset of the rows
+//                 in the matrices
 //       MFMA    : variant = register mask (k = 4, 5 of r = 5); w1,w2 = offset of the real-embedded
 //                 matrix in matrix-core operand order (complex64 only)
 //       SIGN_REG: w3 = mask over registers (bit m set: negate register m)
 //       SIGN_ROW: w1 = tmask; w3 = word offset in the table of 2^kt row masks
 //       ROT     : variant = register mask; w1,w2 = offset of (a, b) per set bit, ascending
+//       MCX     : variant = target register position (bits 0-2) | control register mask << 3
+//       SWAPR   : variant = register position a (bits 0-2) | position b << 3 (a < b)
 //       (blocks without dense ops hold an even op count per phase; a SIGN_REG with k = 0 and
 //       an empty mask pads)
 // The table (per-lane data of diagonal ops) is copied into LDS, after the

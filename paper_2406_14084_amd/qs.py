@@ -49,7 +49,7 @@ class PlanStats_C(C.Structure):
                 ("flops_per_amp", C.c_double), ("hbm_bytes", C.c_double), ("plan_seconds", C.c_double),
                 ("planner", C.c_int), ("candidates", C.c_int), ("predicted_ms", C.c_double),
                 ("predicted_heuristic_ms", C.c_double), ("ops_mfma", C.c_int),
-                ("ops_rot", C.c_int)]
+                ("ops_rot", C.c_int), ("ops_perm", C.c_int)]
 
 
 class QaoaInst_C(C.Structure):

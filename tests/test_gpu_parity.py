@@ -316,3 +316,57 @@ def test_gbg_op_kinds_circuit(torch):
         st.init_zero()
         st.apply_circuit_gbg(c)
         assert max_abs_diff(st.numpy(), sim.run(c)) <= TOL_C128, two
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_diagonal_rows_lds_and_device_memory(torch, dtype):
+    """Per-lane diagonal rows hold entries over the op's register bits only;
+    a block whose tables exceed the LDS share reads the rest from device
+    memory.  Both paths against the oracle."""
+    n = 13
+    rng = np.random.default_rng(7)
+    c = I.Circuit(n)
+    for _ in range(40):
+        tg = tuple(int(x) for x in rng.choice(n, 5, replace=False))
+        c.add("D5", tg, np.diag(np.exp(1j * rng.uniform(0, 6.3, 32))))
+        c.add("H", (int(rng.integers(n)),), I.g_h())
+    say("diag rows", dtype)
+    st = qs.State(n, dtype)
+    st.init_zero()
+    st.apply_plan(qs.Plan(c, kmax=5, chunk_qubits=13, reg_qubits=3, dtype=dtype))
+    d = max_abs_diff(st.numpy().astype(np.complex128), sim.run(c))
+    assert d <= (TOL_C128 if dtype == "c128" else 1e-6), d
+
+
+@pytest.mark.parametrize("dtype,reg", [("c128", 0), ("c128", 3), ("c64", 0)])
+def test_permutation_ops_vs_oracle(torch, dtype, reg):
+    """X, CX, CCX and SWAP run as permutation ops of the blocked pass
+    (register moves, no arithmetic): a pure permutation circuit on a random
+    state is bit-exact against the oracle, and the same gates mixed with U3
+    and the U3 + CX recipe match it within the tolerance."""
+    from tests.test_kernel_replay import _perm_circuit
+    n = 18
+    rng = np.random.default_rng(2)
+    psi0 = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    if dtype == "c64":
+        psi0 = psi0.astype(np.complex64).astype(np.complex128)
+    c = _perm_circuit(n, 300, 11, with_rot=False)
+    p = qs.Plan(c, kmax=5, dtype=dtype, reg_qubits=reg)
+    assert p.stats()["ops_perm"] > 0 and p.stats()["flops_per_amp"] == 0
+    say("perm exact", dtype, reg)
+    st = qs.State(n, dtype)
+    st.tensor.copy_(torch.from_numpy(psi0).to(tdt))
+    st.apply_plan(p)
+    want = psi0.copy()
+    sim.apply_circuit(want, c)
+    assert np.array_equal(st.numpy().astype(np.complex128), want)
+    tol = 2e-6 if dtype == "c64" else TOL_C128
+    for c in (_perm_circuit(n, 300, 12, with_rot=True), I.random_u3_2q(n=n, depth=12, seed=5, two="CX")):
+        p = qs.Plan(c, kmax=5, dtype=dtype, reg_qubits=reg)
+        assert p.stats()["ops_perm"] > 0
+        say("perm mixed", dtype, reg, len(c))
+        st.init_zero()
+        st.apply_plan(p)
+        d = max_abs_diff(st.numpy().astype(np.complex128), sim.run(c))
+        assert d <= tol, d

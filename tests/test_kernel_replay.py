@@ -235,6 +235,17 @@ def replay_block(psi, w, n, R, mats, c64=False):
                     res = np.einsum("rc,wtc->wtr", M, vin)
                     out[:, :, cols] = res
                 v = out
+            elif kind == 9:       # multi-controlled X: flip register bit t where the control bits are set
+                t, ctrl = variant & 7, variant >> 3
+                assert t < R and ctrl < NR and not (ctrl >> t) & 1
+                src = np.array([m ^ (1 << t) if (m & ctrl) == ctrl else m for m in range(NR)])
+                v = v[:, :, src]
+            elif kind == 10:      # SWAP of register bits a < b
+                a, b = variant & 7, variant >> 3
+                assert a < b < R
+                src = np.array([(m & ~((1 << a) | (1 << b))) | (((m >> a) & 1) << b) | (((m >> b) & 1) << a)
+                                for m in range(NR)])
+                v = v[:, :, src]
             elif kind == 6:       # one 2x2 gate per register bit of the mask, ascending
                 idx = 0
                 for j in range(R):
@@ -272,18 +283,21 @@ def replay_block(psi, w, n, R, mats, c64=False):
                 tmask = int(w[op + 1])
                 row = _pext(tid, tmask)
                 kt = bin(tmask).count("1")
-                if variant == 1:  # rows in device memory (table too large for LDS)
+                rm = variant >> 1  # register positions of the op: 2^kr entries per row
+                assert rm < NR and variant < 64
+                ne = 1 << bin(rm).count("1")
+                ent = np.array([_pext(m, rm) for m in range(NR)])
+                if variant & 1:   # rows in device memory (table too large for LDS)
                     goff = int(np.uint32(w[op + 2])) | (int(w[op + 3]) << 32)
-                    E = mats[goff:goff + 2 * NR * (1 << kt)].view(np.complex128).reshape(1 << kt, NR)
+                    E = mats[goff:goff + 2 * ne * (1 << kt)].view(np.complex128).reshape(1 << kt, ne)
                 else:             # rows in the LDS table
-                    assert variant == 0
                     wpe = 2 if c64 else 4
                     a = tab_off + int(w[op + 3])
-                    assert a % 4 == 0 and int(w[op + 3]) + wpe * NR * (1 << kt) <= tab_words
-                    raw = np.ascontiguousarray(w[a:a + wpe * NR * (1 << kt)])
+                    assert a % 4 == 0 and int(w[op + 3]) + wpe * ne * (1 << kt) <= tab_words
+                    raw = np.ascontiguousarray(w[a:a + wpe * ne * (1 << kt)])
                     E = (raw.view(np.complex64).astype(np.complex128) if c64 else raw.view(np.complex128))
-                    E = E.reshape(1 << kt, NR)
-                v = v * E[row][None, :, :]
+                    E = E.reshape(1 << kt, ne)
+                v = v * E[row][:, ent][None, :, :]
             elif kind == 7:       # complex64 dense op on matrix cores, emulated lane by lane
                 v = _replay_mfma(v, variant, k, mats[moff:], R, tb)
             elif kind == 4:       # +-1 on registers
@@ -323,10 +337,13 @@ def replay_block(psi, w, n, R, mats, c64=False):
     return out
 
 
-def replay_plan(plan, n):
+def replay_plan(plan, n, psi0=None):
     w, offs, R, C, mats = plan.program()
-    psi = np.zeros(1 << n, dtype=np.complex128)
-    psi[0] = 1
+    if psi0 is None:
+        psi = np.zeros(1 << n, dtype=np.complex128)
+        psi[0] = 1
+    else:
+        psi = np.array(psi0, dtype=np.complex128)
     c64 = plan.stats()["dtype"] == 1
     for o in offs:
         psi = replay_block(psi, w[o:], n, R, mats, c64)
@@ -481,7 +498,7 @@ def _diag_row_variants(p):
             nops = int(w[ph]); op = ph + PHASE_HDR + C + 2 * (C - R) + 2 * (1 << R)
             for _ in range(nops):
                 if int(w[op]) & 0xff == 3:
-                    out.add((int(w[op]) >> 8) & 0xff)
+                    out.add((int(w[op]) >> 8) & 1)
                 op += OP_WORDS
             ph = op
     return out
@@ -529,17 +546,65 @@ def test_matrix_core_ops_need_full_waves():
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_replay_large_diagonal_tables_spill(dtype):
     """Diagonals merged over many thread bits make row tables larger than the
-    LDS left beside a 13-qubit chunk; those tables are read from device memory
-    (DIAG_ROW variant 1) and the replay still matches the oracle."""
-    n = 16
+    16 KiB the LDS keeps for tables; those tables are read from device memory
+    (DIAG_ROW variant bit 0) and the replay still matches the oracle."""
+    n = 13        # one block: every diagonal of the circuit lands in one table
     rng = np.random.default_rng(7)
     c = I.Circuit(n)
     for _ in range(40):
-        tg = tuple(int(x) for x in rng.choice(n, 4, replace=False))
-        c.add("D4", tg, np.diag(np.exp(1j * rng.uniform(0, 6.3, 16))))
+        tg = tuple(int(x) for x in rng.choice(n, 5, replace=False))
+        c.add("D5", tg, np.diag(np.exp(1j * rng.uniform(0, 6.3, 32))))
         c.add("H", (int(rng.integers(n)),), I.g_h())
     p = qs.Plan(c, kmax=5, chunk_qubits=13, reg_qubits=3, dtype=dtype)
-    # complex64 tables are half the size and fit beside the (half-size) chunk
-    assert _diag_row_variants(p) == ({0, 1} if dtype == "c128" else {0})
+    assert _diag_row_variants(p) == {0, 1}
     tol = 1e-7 if dtype == "c64" else 1e-12
     assert np.max(np.abs(replay_plan(p, n) - sim.run(c))) <= tol
+
+
+def _perm_circuit(n, ngates, seed, with_rot=True):
+    """X, CX (both orientations), CCX and SWAP on random qubits, optionally
+    interleaved with U3 gates."""
+    rng = np.random.default_rng(seed)
+    c = I.Circuit(n)
+    for _ in range(ngates):
+        kind = int(rng.integers(0, 5 if with_rot else 4))
+        if kind == 0:
+            c.add("X", (int(rng.integers(n)),), I.g_x())
+        elif kind == 1:
+            c.add("CX", tuple(int(x) for x in rng.choice(n, 2, replace=False)), I.g_cx())
+        elif kind == 2:
+            m = np.eye(8, dtype=np.complex128)
+            m[[6, 7]] = m[[7, 6]]
+            c.add("CCX", tuple(int(x) for x in rng.choice(n, 3, replace=False)), m)
+        elif kind == 3:
+            c.add("SWAP", tuple(int(x) for x in rng.choice(n, 2, replace=False)), I.g_swap())
+        else:
+            c.add("U3", (int(rng.integers(n)),), I.g_u3(*rng.uniform(0, 6.3, 3)))
+    return c
+
+
+@pytest.mark.parametrize("dtype,reg", [("c128", 0), ("c128", 3), ("c64", 0)])
+def test_replay_permutation_ops(dtype, reg):
+    """X, CX, CCX and SWAP become permutation ops (register moves, no
+    arithmetic): a pure permutation circuit replays bit for bit, and one mixed
+    with U3 gates matches the oracle; U3 + CX plans no longer fuse the CXs
+    into dense two-qubit ops."""
+    n = 14
+    c = _perm_circuit(n, 200, 5, with_rot=False)
+    p = qs.Plan(c, kmax=5, dtype=dtype, reg_qubits=reg)
+    s = p.stats()
+    assert s["ops_perm"] > 0 and s["flops_per_amp"] == 0 and {9, 10} <= _op_kinds(p)
+    rng = np.random.default_rng(1)
+    psi0 = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    got = replay_plan(p, n, psi0=psi0)
+    want = psi0.copy()
+    sim.apply_circuit(want, c)
+    assert np.array_equal(got, want)
+    c = _perm_circuit(n, 200, 6, with_rot=True)
+    p = qs.Plan(c, kmax=5, dtype=dtype, reg_qubits=reg)
+    assert p.stats()["ops_perm"] > 0
+    tol = 1e-6 if dtype == "c64" else 1e-12
+    assert np.max(np.abs(replay_plan(p, n) - sim.run(c))) <= tol
+    c = I.random_u3_2q(n=20, depth=8, seed=3, two="CX")
+    s = qs.Plan(c, kmax=5, dtype=dtype).stats()
+    assert s["ops_perm"] > 0 and s["ops_dense"][2] + s["ops_dense"][3] < s["ops_perm"], s
