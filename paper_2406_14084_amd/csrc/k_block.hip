@@ -196,68 +196,58 @@ __device__ __forceinline__ void rot_dispatch(int mask, V (&v)[1 << R], P M)
 }
 #undef QS_ROT_CASE
 
-// Permutation ops: no arithmetic, the compile-time register indices move.
-// Multi-controlled X: flip register bit T of every register whose CTRL bits are
-// all set (X: CTRL = 0, CX: one control, CCX: two).
-template <int R, int T, int CTRL, typename V>
-__device__ __forceinline__ void apply_mcx(V (&v)[1 << R])
+// Permutation op (multi-controlled X: X, CX, CCX): flip register bit T of every
+// register whose bits in ctrl (uniform, bit T clear) are all set.  No
+// arithmetic: each pair (m, m | 1 << T) swaps its bit patterns under a uniform
+// mask.  (A switch over every (target, controls) pattern with compile-time
+// moves, or selects between the pair, make the compiler index the register
+// array dynamically, which puts the whole state in scratch memory.)  SWAP is
+// encoded as three of these.
+// exchange a and b where the uniform mask k is all ones: (a, b) ^= ((a ^ b) & k)
+__device__ __forceinline__ void cswap(double &a, double &b, uint64_t k)
+{
+    const uint64_t x = __double_as_longlong(a), y = __double_as_longlong(b);
+    const uint64_t d = (x ^ y) & k;
+    a = __longlong_as_double(x ^ d);
+    b = __longlong_as_double(y ^ d);
+}
+__device__ __forceinline__ void cswap(float &a, float &b, uint64_t k)
+{
+    const uint32_t x = __float_as_uint(a), y = __float_as_uint(b);
+    const uint32_t d = (x ^ y) & (uint32_t)k;
+    a = __uint_as_float(x ^ d);
+    b = __uint_as_float(y ^ d);
+}
+
+template <int R, int T, typename V>
+__device__ __forceinline__ void apply_mcx(V (&v)[1 << R], uint32_t ctrl)
 {
 #pragma unroll
     for (int m = 0; m < (1 << R); ++m) {
-        if ((m & CTRL) != CTRL || ((m >> T) & 1)) continue;
-        const V t = v[m];
-        v[m] = v[m | (1 << T)];
-        v[m | (1 << T)] = t;
+        if ((m >> T) & 1) continue;
+        // all ones where register m's control bits are set (uniform, a scalar value)
+        const uint64_t k = 0ull - (uint64_t)(((uint32_t)m & ctrl) == ctrl);
+        cswap(v[m].x, v[m | (1 << T)].x, k);
+        cswap(v[m].y, v[m | (1 << T)].y, k);
+        // opaque to the optimiser: the cases of the dispatch switch must not be
+        // merged into one that indexes the register array by a runtime value
+        asm volatile("" : "+v"(v[m].x), "+v"(v[m].y), "+v"(v[m | (1 << T)].x), "+v"(v[m | (1 << T)].y));
     }
 }
 
-// SWAP: exchange register bits A and B.
-template <int R, int A, int B, typename V>
-__device__ __forceinline__ void apply_swapr(V (&v)[1 << R])
+template <int R, typename V>
+__device__ __forceinline__ void mcx_dispatch(int var, V (&v)[1 << R])
 {
-#pragma unroll
-    for (int m = 0; m < (1 << R); ++m) {
-        if (((m >> A) & 1) != 1 || ((m >> B) & 1) != 0) continue;
-        const int m2 = (m & ~(1 << A)) | (1 << B);
-        const V t = v[m];
-        v[m] = v[m2];
-        v[m2] = t;
+    const uint32_t ctrl = (uint32_t)var >> 3;
+    switch (var & 7) {
+    case 0: apply_mcx<R, 0, V>(v, ctrl); break;
+    case 1: if constexpr (R > 1) apply_mcx<R, (R > 1 ? 1 : 0), V>(v, ctrl); else __builtin_unreachable(); break;
+    case 2: if constexpr (R > 2) apply_mcx<R, (R > 2 ? 2 : 0), V>(v, ctrl); else __builtin_unreachable(); break;
+    case 3: if constexpr (R > 3) apply_mcx<R, (R > 3 ? 3 : 0), V>(v, ctrl); else __builtin_unreachable(); break;
+    case 4: if constexpr (R > 4) apply_mcx<R, (R > 4 ? 4 : 0), V>(v, ctrl); else __builtin_unreachable(); break;
+    default: __builtin_unreachable();
     }
 }
-
-// variant = T | CTRL << 3 for MCX, A | B << 3 for SWAPR; values the host never
-// encodes (checked when the program is built) are unreachable
-#define QS_PERM_CASE(VV)                                                                            \
-    case VV:                                                                                        \
-        if constexpr (SW) {                                                                         \
-            if constexpr (((VV) & 7) < ((VV) >> 3) && ((VV) >> 3) < R)                              \
-                apply_swapr<R, ((VV) & 7), (((VV) >> 3) < R ? ((VV) >> 3) : 0), V>(v);              \
-            else                                                                                    \
-                __builtin_unreachable();                                                            \
-        } else {                                                                                    \
-            if constexpr (((VV) & 7) < R && ((VV) >> 3) < (1 << R) && !((((VV) >> 3) >> ((VV) & 7)) & 1)) \
-                apply_mcx<R, (((VV) & 7) < R ? ((VV) & 7) : 0), ((VV) >> 3), V>(v);                 \
-            else                                                                                    \
-                __builtin_unreachable();                                                            \
-        }                                                                                           \
-        break;
-#define QS_PERM_C4(X) QS_PERM_CASE(X) QS_PERM_CASE(X + 1) QS_PERM_CASE(X + 2) QS_PERM_CASE(X + 3)
-#define QS_PERM_C16(X) QS_PERM_C4(X) QS_PERM_C4(X + 4) QS_PERM_C4(X + 8) QS_PERM_C4(X + 12)
-#define QS_PERM_C64(X) QS_PERM_C16(X) QS_PERM_C16(X + 16) QS_PERM_C16(X + 32) QS_PERM_C16(X + 48)
-
-template <int R, bool SW, typename V>
-__device__ __forceinline__ void perm_dispatch(int var, V (&v)[1 << R])
-{
-    switch (var) {
-        QS_PERM_C64(0) QS_PERM_C64(64) QS_PERM_C64(128) QS_PERM_C64(192)
-    default:
-        __builtin_unreachable();
-    }
-}
-#undef QS_PERM_C64
-#undef QS_PERM_C16
-#undef QS_PERM_C4
-#undef QS_PERM_CASE
 
 // bits of v selected by MASK, packed to the low end (compile time)
 template <int MASK>
@@ -485,7 +475,7 @@ template <int R, typename F, bool MF> struct MinWaves {
 };
 
 template <int R, int KMAX, typename F, bool MF>
-__global__ __launch_bounds__(MaxThreads<R>::value) __attribute__((amdgpu_waves_per_eu(MinWaves<R, F, MF>::value)))
+__global__ __launch_bounds__(MaxThreads<R>::value) __attribute__((amdgpu_waves_per_eu(MinWaves<R, F, MF>::value, MinWaves<R, F, MF>::value)))
 void k_block(typename AmpOf<F>::type *__restrict__ amps,
                                               const int *__restrict__ prog, const F *__restrict__ mats, int n)
 {
@@ -633,11 +623,15 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
                     if constexpr (KMAX > 0) multi1_dispatch<R, F, V, const CF *>(variant, v, M);
                     else __builtin_unreachable();
                 } else if (kind == OP_MCX) {
-                    perm_dispatch<R, false, V>(variant, v);
-                } else if (kind == OP_SWAPR) {
-                    perm_dispatch<R, true, V>(variant, v);
-                } else if (kind == OP_ROT) {
+                    mcx_dispatch<R, V>(variant, v);
+                } else if (kind == OP_ROT || kind == OP_ROTD) {
+                    // one copy of the rotation paths for both kinds (code size)
                     rot_dispatch<R, F, V, const CF *>(variant, v, M);
+                    if (kind == OP_ROTD) {
+                        const CF *D = M + 2 * __builtin_popcount((uint32_t)variant);
+#pragma unroll
+                        for (int m = 0; m < NR; ++m) v[m] = cmul<F, V>(D[2 * m], D[2 * m + 1], v[m]);
+                    }
                 } else if (kind == OP_DENSE) {
                     if constexpr (KMAX > 0) dense_dispatch<R, KMAX, F, V, const CF *>(variant, v, M);
                     else __builtin_unreachable();

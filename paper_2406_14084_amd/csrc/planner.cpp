@@ -1138,7 +1138,21 @@ qs_status build_plan(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan 
             std::vector<Op> kops;
             std::vector<SetOp> fused = PS.fuse_phase(phase_ops, R);
             if (opts.enable_fusion) fused = PS.reschedule(fused, R);
-            for (const SetOp &s : fused) kops.push_back(to_kernel_op(s, ph.lay, r));
+            for (const SetOp &s : fused) {
+                Op k = to_kernel_op(s, ph.lay, r);
+                if (k.kind == OP_SWAPR) {
+                    // SWAP(a, b) = CX(a -> b) CX(b -> a) CX(a -> b): three permutation ops
+                    const int a = __builtin_ctz((unsigned)k.regmask), b = 31 - __builtin_clz((unsigned)k.regmask);
+                    for (int t : {b, a, b}) {
+                        Op x = k;
+                        x.kind = OP_MCX;
+                        x.ptarget = t;
+                        kops.push_back(x);
+                    }
+                    continue;
+                }
+                kops.push_back(k);
+            }
             ph.ops = opts.enable_fusion ? group_single_qubit(kops, ph.lay, r) : kops;
             blk.phases.push_back(ph);
             first = false;
@@ -1437,9 +1451,8 @@ static void check_program(const Plan &p)
                 switch (kind) {
                 case OP_DENSE: ok = var > 0 && var < NR && __builtin_popcount(var) <= kw; break;
                 case OP_MULTI1: ok = kw >= 1 && var > 0 && var < NR; break;
-                case OP_ROT: ok = var > 0 && var < NR; break;
+                case OP_ROT: case OP_ROTD: ok = var > 0 && var < NR; break;
                 case OP_MCX: ok = (var & 7) < r && (var >> 3) < NR && !(((var >> 3) >> (var & 7)) & 1); break;
-                case OP_SWAPR: ok = (var & 7) < (var >> 3) && (var >> 3) < r; break;
                 case OP_MFMA:
                     ok = bm && r == 5 && (var == 15 || var == 23 || var == 27 || var == 29 || var == 30 || var == 31);
                     break;
@@ -1577,15 +1590,57 @@ void encode_plan(Plan *p)
             }
             // blocks without dense ops run two ops per loop trip: an odd phase gets a
             // leading no-op (a sign op with an empty mask)
-            if (bk == 0 && !bm && (P.ops.size() & 1)) {
-                w[hdr] = (int32_t)P.ops.size() + 1;
+            // a rotation op followed by a diagonal on register bits only (not +-1) runs as one
+            // op (OP_ROTD: the shears, then the diagonal): one dispatch instead of two
+            auto reg_only_diag = [&](const Op &d) {
+                if (d.kind != OP_DIAG) return false;
+                for (int i = 0; i < d.k; ++i) {
+                    bool in_r = false;
+                    for (int j = 0; j < r; ++j) in_r |= P.lay.R[j] == d.tl[i];
+                    if (!in_r) return false;
+                }
+                for (const cplx &z : d.m)
+                    if (!(z.imag() == 0.0 && (z.real() == 1.0 || z.real() == -1.0))) return true;
+                return false;
+            };
+            std::vector<char> fuse_next(P.ops.size(), 0);
+            size_t nenc = P.ops.size();
+            for (size_t i = 0; i + 1 < P.ops.size(); ++i)
+                if (P.ops[i].kind == OP_ROT && reg_only_diag(P.ops[i + 1]) && !(i > 0 && fuse_next[i - 1])) {
+                    fuse_next[i] = 1;
+                    --nenc;
+                }
+            w[hdr] = (int32_t)nenc;
+            if (bk == 0 && !bm && (nenc & 1)) {
+                w[hdr] = (int32_t)nenc + 1;
                 w.push_back(OP_SIGN_REG);
                 w.push_back(0);
                 w.push_back(0);
                 w.push_back(0);
             }
-            for (const Op &op : P.ops) {
+            for (size_t oi = 0; oi < P.ops.size(); ++oi) {
+                const Op &op = P.ops[oi];
                 int64_t moff = (int64_t)p->h_mats.size();
+                if (fuse_next[oi]) {
+                    // (a, b) per rotated register bit, then the 2^r diagonal entries in register order
+                    const Op &d = P.ops[oi + 1];
+                    for (const cplx &z : op.m) { p->h_mats.push_back(z.real()); p->h_mats.push_back(z.imag()); }
+                    for (int m = 0; m < NR; ++m) {
+                        uint32_t l = 0;
+                        for (int j = 0; j < r; ++j)
+                            if (m >> j & 1) l |= 1u << P.lay.R[j];
+                        int idx = 0;
+                        for (int t = 0; t < d.k; ++t) idx |= (int)((l >> d.tl[t]) & 1) << t;
+                        p->h_mats.push_back(d.m[idx].real());
+                        p->h_mats.push_back(d.m[idx].imag());
+                    }
+                    w.push_back(OP_ROTD | (op.regmask << 8) | (op.k << 16));
+                    w.push_back((int32_t)(uint32_t)(moff & 0xffffffff));
+                    w.push_back((int32_t)(uint32_t)(moff >> 32));
+                    w.push_back(0);
+                    ++oi;
+                    continue;
+                }
                 if (op.kind == OP_DENSE && p->mfma && op.k >= 4) {
                     // Matrix-core form: the real embedding [[Re U, -Im U], [Im U, Re U]] of U,
                     // stored in the order the kernel feeds the 32x32x2 FP32 product: block mb
@@ -1609,16 +1664,9 @@ void encode_plan(Plan *p)
                     w.push_back(0);
                     continue;
                 }
-                if (op.kind == OP_MCX || op.kind == OP_SWAPR) {
-                    int var;
-                    if (op.kind == OP_MCX) {
-                        var = op.ptarget | ((op.regmask & ~(1 << op.ptarget)) << 3);
-                    } else {
-                        const int a = __builtin_ctz((unsigned)op.regmask);
-                        const int b = 31 - __builtin_clz((unsigned)op.regmask);
-                        var = a | (b << 3);
-                    }
-                    w.push_back(op.kind | (var << 8) | (op.k << 16));
+                if (op.kind == OP_MCX) {
+                    const int var = op.ptarget | ((op.regmask & ~(1 << op.ptarget)) << 3);
+                    w.push_back(OP_MCX | (var << 8) | (op.k << 16));
                     w.push_back(0);
                     w.push_back(0);
                     w.push_back(0);

@@ -39,7 +39,8 @@ enum OpKind {
                        // x0 += a x1, x1 += b x0, x0 += a x1 (coefficients (a, b) per bit, ascending)
     OP_MCX = 9,        // permutation, no arithmetic: flip register bit ptarget of every register whose
                        // bits in regmask & ~(1 << ptarget) (the controls) are all set (X, CX, CCX)
-    OP_SWAPR = 10      // permutation, no arithmetic: exchange the two register bits of regmask (SWAP)
+    OP_SWAPR = 10,     // planner only: SWAP of the two register bits of regmask, encoded as three OP_MCX
+    OP_ROTD = 11       // encoding only: an OP_ROT followed by a diagonal on register bits, in one op
 };
 
 struct Op {
@@ -144,7 +145,8 @@ qs_status build_plan_search(const qs_circuit *c, int kmax, const qs_plan_opts *o
 //       SIGN_ROW: w1 = tmask; w3 = word offset in the table of 2^kt row masks
 //       ROT     : variant = register mask; w1,w2 = offset of (a, b) per set bit, ascending
 //       MCX     : variant = target register position (bits 0-2) | control register mask << 3
-//       SWAPR   : variant = register position a (bits 0-2) | position b << 3 (a < b)
+//       ROTD    : variant = register mask; w1,w2 = offset of (a, b) per set bit, ascending, then
+//                 the 2^r entries of a diagonal in register order (applied after the shears)
 //       (blocks without dense ops hold an even op count per phase; a SIGN_REG with k = 0 and
 //       an empty mask pads)
 // The table (per-lane data of diagonal ops) is copied into LDS, after the

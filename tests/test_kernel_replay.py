@@ -260,7 +260,8 @@ def replay_block(psi, w, n, R, mats, c64=False):
                         out[:, :, cols] = np.einsum("rc,wtc->wtr", M, v[:, :, cols])
                     v = out
                     idx += 1
-            elif kind == 8:       # real rotation per register bit, as three shears, ascending
+            elif kind == 8 or kind == 11:  # real rotation per register bit (shears), ascending;
+                # kind 11: then a diagonal on the registers (2^R entries after the coefficients)
                 idx = 0
                 for j in range(R):
                     if not (variant >> j) & 1:
@@ -276,6 +277,9 @@ def replay_block(psi, w, n, R, mats, c64=False):
                     v = v.copy()
                     v[:, :, lo], v[:, :, hi] = x0, x1
                     idx += 1
+                if kind == 11:
+                    E = mats[moff + 2 * idx:moff + 2 * idx + 2 * NR].view(np.complex128)
+                    v = v * E[None, None, :]
             elif kind == 2:       # register diagonal: uniform entry per register
                 E = mats[moff:moff + 2 * NR].view(np.complex128)
                 v = v * E[None, None, :]
@@ -418,7 +422,7 @@ def test_replay_uses_every_diagonal_encoding():
     """Circuits with general and +-1 diagonals exercise the register, row and
     sign encodings of diagonal ops; with single-qubit gates split (phase,
     rotation, phase) and kept whole, also the rotation and grouped
-    single-qubit encodings."""
+    single-qubit encodings, and rotations fused with the diagonal after them."""
     n = 13
     kinds = set()
     for seed in range(4):
@@ -433,7 +437,7 @@ def test_replay_uses_every_diagonal_encoding():
                 p = qs.Plan(cc, kmax=4, split=split)
                 kinds |= _op_kinds(p)
                 assert np.max(np.abs(replay_plan(p, cc.n) - sim.run(cc))) <= 1e-12
-    assert {0, 2, 3, 4, 5, 6, 8} <= kinds, kinds
+    assert {0, 2, 3, 4, 5, 6, 8, 11} <= kinds, kinds
 
 
 def test_split_needs_a_unitary_gate():
@@ -593,7 +597,7 @@ def test_replay_permutation_ops(dtype, reg):
     c = _perm_circuit(n, 200, 5, with_rot=False)
     p = qs.Plan(c, kmax=5, dtype=dtype, reg_qubits=reg)
     s = p.stats()
-    assert s["ops_perm"] > 0 and s["flops_per_amp"] == 0 and {9, 10} <= _op_kinds(p)
+    assert s["ops_perm"] > 0 and s["flops_per_amp"] == 0 and 9 in _op_kinds(p) and 10 not in _op_kinds(p)
     rng = np.random.default_rng(1)
     psi0 = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
     got = replay_plan(p, n, psi0=psi0)
