@@ -560,12 +560,12 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
                 const uint32_t hx = (uint32_t)ph[3] >> 24;
                 const int hjw = (int)(hx & 15u) - 1, hjr = (int)(hx >> 4) - 1;
                 if (xt > 0) {
-                    const int *Xl = ltab + (xt - 1);    // the same words, staged in LDS
-                    for (int j = 0; j < tb; ++j) {
-                        const uint32_t sel = 0u - ((tid >> j) & 1u);
-                        wt ^= (uint32_t)Xl[j] & sel;
-                        rt ^= (uint32_t)Xl[tb + j] & sel;
-                    }
+                    // per-nibble XOR tables of the same words, staged in LDS
+                    const int *Xl = ltab + (xt - 1);
+                    const uint32_t n0 = tid & 15u, n1 = (tid >> 4) & 15u, n2 = (tid >> 8) & 1u;
+                    wt = (uint32_t)Xl[n0] ^ (uint32_t)Xl[16 + n1] ^ (uint32_t)Xl[32 + n2];
+                    rt = (uint32_t)Xl[kNibWords + n0] ^ (uint32_t)Xl[kNibWords + 16 + n1] ^
+                         (uint32_t)Xl[kNibWords + 32 + n2];
                 } else {
                     for (int j = 0; j < tb; ++j) {
                         const uint32_t sel = 0u - ((tid >> j) & 1u);
@@ -582,6 +582,31 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
                     lds_barrier();      // every write is visible
 #pragma unroll
                     for (int m = 0; m < NR; ++m) v[m] = *reinterpret_cast<const V *>(lds_raw + (rt ^ (uint32_t)ro[m]));
+                } else if (hjw >= 6) {
+                    // two rounds through half the buffer, the split bit a wave-index bit: a whole
+                    // wave writes and reads in one round (uniform branch, four barriers for every
+                    // wave); each side redefines all its registers from LDS, so no register
+                    // copies merge the two sides
+                    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+                    const bool first = ((wave >> (hjw - 6)) & 1u) == 0;
+                    lds_barrier();
+                    if (first) {
+#pragma unroll
+                        for (int m = 0; m < NR; ++m) *reinterpret_cast<V *>(lds_raw + (wt ^ (uint32_t)wo[m])) = v[m];
+                        lds_barrier();
+#pragma unroll
+                        for (int m = 0; m < NR; ++m) v[m] = *reinterpret_cast<const V *>(lds_raw + (rt ^ (uint32_t)ro[m]));
+                        lds_barrier();
+                        lds_barrier();
+                    } else {
+                        lds_barrier();
+                        lds_barrier();
+#pragma unroll
+                        for (int m = 0; m < NR; ++m) *reinterpret_cast<V *>(lds_raw + (wt ^ (uint32_t)wo[m])) = v[m];
+                        lds_barrier();
+#pragma unroll
+                        for (int m = 0; m < NR; ++m) v[m] = *reinterpret_cast<const V *>(lds_raw + (rt ^ (uint32_t)ro[m]));
+                    }
                 } else {
                     // two rounds through half the buffer: the threads whose bit hjw (= hjr, the
                     // planner keeps the split bit at one position) is h hold exactly the
@@ -619,7 +644,9 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
                 const CF *M = (const CF *)(uintptr_t)(mats + ((int64_t)mlo | ((int64_t)mhi << 32)));
                 // KMAX == 0: a block of rotations and diagonals only (no dense paths
                 // compiled in: less code and fewer registers)
-                if (kind == OP_MULTI1) {
+                if (kind == OP_NOP) {
+                    // padding: nothing
+                } else if (kind == OP_MULTI1) {
                     if constexpr (KMAX > 0) multi1_dispatch<R, F, V, const CF *>(variant, v, M);
                     else __builtin_unreachable();
                 } else if (kind == OP_MCX) {

@@ -1456,7 +1456,7 @@ static void check_program(const Plan &p)
                 case OP_MFMA:
                     ok = bm && r == 5 && (var == 15 || var == 23 || var == 27 || var == 29 || var == 30 || var == 31);
                     break;
-                case OP_DIAG_REG: case OP_DIAG_ROW: case OP_SIGN_REG: case OP_SIGN_ROW: ok = true; break;
+                case OP_DIAG_REG: case OP_DIAG_ROW: case OP_SIGN_REG: case OP_SIGN_ROW: case OP_NOP: ok = true; break;
                 default: ok = false;
                 }
                 if (!ok)
@@ -1581,15 +1581,29 @@ void encode_plan(Plan *p)
                     for (size_t i = x0; i < w.size(); ++i) w[i] = (int32_t)drop((uint32_t)w[i]);
                     w[hdr + 3] |= (int32_t)((uint32_t)(split_w[ph] + 1) << 24 | (uint32_t)(split_r[ph] + 1) << 28);
                 }
-                // a copy of the thread-bit words in the LDS table (header word 3, low 24
-                // bits = its offset + 1): the kernel reads them per lane without global loads
-                if (has && tab.size() + 2 * (size_t)(C - r) <= tab_cap) {
+                // the thread's XOR of its bits' words, tabulated per nibble of the thread
+                // index in the LDS table (header word 3, low 24 bits = its offset + 1):
+                // write side W0[16] (thread bits 0-3), W1[16] (4-7), W2[2] (8), then the
+                // read side the same way; the kernel forms each with three table reads
+                if (has && tab.size() + 2 * kNibWords <= tab_cap) {
                     w[hdr + 3] |= (int32_t)tab.size() + 1;
-                    tab.insert(tab.end(), w.begin() + xw0, w.begin() + xw0 + 2 * (C - r));
+                    const int tbits = C - r;
+                    for (int side = 0; side < 2; ++side) {
+                        const int32_t *xw = w.data() + xw0 + (size_t)side * tbits;
+                        for (int part = 0; part < 3; ++part) {
+                            const int lo = 4 * part, cnt = part < 2 ? 16 : 2;
+                            for (int e = 0; e < cnt; ++e) {
+                                uint32_t acc = 0;
+                                for (int j = lo; j < lo + 4 && j < tbits; ++j)
+                                    if (e >> (j - lo) & 1) acc ^= (uint32_t)xw[j];
+                                tab.push_back((int32_t)acc);
+                            }
+                        }
+                    }
                 }
             }
             // blocks without dense ops run two ops per loop trip: an odd phase gets a
-            // leading no-op (a sign op with an empty mask)
+            // leading no-op (OP_NOP)
             // a rotation op followed by a diagonal on register bits only (not +-1) runs as one
             // op (OP_ROTD: the shears, then the diagonal): one dispatch instead of two
             auto reg_only_diag = [&](const Op &d) {
@@ -1613,7 +1627,7 @@ void encode_plan(Plan *p)
             w[hdr] = (int32_t)nenc;
             if (bk == 0 && !bm && (nenc & 1)) {
                 w[hdr] = (int32_t)nenc + 1;
-                w.push_back(OP_SIGN_REG);
+                w.push_back(OP_NOP);
                 w.push_back(0);
                 w.push_back(0);
                 w.push_back(0);

@@ -40,8 +40,12 @@ enum OpKind {
     OP_MCX = 9,        // permutation, no arithmetic: flip register bit ptarget of every register whose
                        // bits in regmask & ~(1 << ptarget) (the controls) are all set (X, CX, CCX)
     OP_SWAPR = 10,     // planner only: SWAP of the two register bits of regmask, encoded as three OP_MCX
-    OP_ROTD = 11       // encoding only: an OP_ROT followed by a diagonal on register bits, in one op
+    OP_ROTD = 11,      // encoding only: an OP_ROT followed by a diagonal on register bits, in one op
+    OP_NOP = 12        // encoding only: pads a phase of a block without dense ops to an even op count
 };
+// words of the per-nibble tables of an exchange's thread-bit words (write and read side each:
+// 16 for thread bits 0-3, 16 for bits 4-7, 2 for bit 8)
+constexpr int kNibWords = 34;
 
 struct Op {
     int kind = OP_DENSE;
@@ -118,8 +122,9 @@ qs_status build_plan_search(const qs_circuit *c, int kmax, const qs_plan_opts *o
 //   [8+C .. 8+2C)     P_out
 //   then per phase:
 //     [0] nops, [1] swz_lo (F nibbles for high bits 0..7), [2] swz_hi (8..15),
-//     [3] bits 0-23: 1 + word offset in the LDS table of a copy of the 2 tb thread-bit words
-//         below, or 0; bits 24-27 / 28-31: 1 + thread position of the split bit in the write /
+//     [3] bits 0-23: 1 + word offset in the LDS table of the per-nibble XOR tables of the
+//         thread-bit words below (write side, then read side, kNibWords each), or 0;
+//         bits 24-27 / 28-31: 1 + thread position of the split bit in the write /
 //         read layout (equal; 0 = one round through the whole buffer); the split bit is then
 //         dropped from every offset of the exchange block
 //     [4 .. 4+r)      R
@@ -147,8 +152,7 @@ qs_status build_plan_search(const qs_circuit *c, int kmax, const qs_plan_opts *o
 //       MCX     : variant = target register position (bits 0-2) | control register mask << 3
 //       ROTD    : variant = register mask; w1,w2 = offset of (a, b) per set bit, ascending, then
 //                 the 2^r entries of a diagonal in register order (applied after the shears)
-//       (blocks without dense ops hold an even op count per phase; a SIGN_REG with k = 0 and
-//       an empty mask pads)
+//       (blocks without dense ops hold an even op count per phase; an OP_NOP pads)
 // The table (per-lane data of diagonal ops) is copied into LDS, after the
 // exchange buffer, once per workgroup.
 // The swizzle for the exchange INTO a phase: slot(l) = l ^ F(l >> 4) where

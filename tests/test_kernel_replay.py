@@ -191,10 +191,17 @@ def replay_block(psi, w, n, R, mats, c64=False):
                 assert np.array_equal(kw[:, None] ^ wo[None, :], ws * ab)
                 assert np.array_equal(kr[:, None] ^ ro[None, :], rs * ab)
             xt = int(w[ph + 3]) & 0xffffff
-            if xt > 0:   # the kernel reads a copy of the thread-bit words from the LDS table
+            if xt > 0:   # the kernel forms kw, kr from per-nibble XOR tables in the LDS table
                 a = xt - 1
-                assert a + 2 * tb <= tab_words
-                assert [int(x) for x in w[tab_off + a:tab_off + a + 2 * tb]] == xw + xr
+                NIB = 34
+                assert a + 2 * NIB <= tab_words and tb <= 9
+                tabv = np.array([int(x) for x in w[tab_off + a:tab_off + a + 2 * NIB]], dtype=np.int64)
+                for side, want in ((0, kw), (1, kr)):
+                    t0 = tabv[side * NIB:side * NIB + 16]
+                    t1 = tabv[side * NIB + 16:side * NIB + 32]
+                    t2 = tabv[side * NIB + 32:side * NIB + 34]
+                    got = t0[tid & 15] ^ t1[(tid >> 4) & 15] ^ t2[(tid >> 8) & 1]
+                    assert np.array_equal(got, want)
             for s in (ws, rs):
                 assert s.min() >= 0 and s.max() < (1 << C)
                 assert np.unique(s).size == s.size == (1 << C), "exchange is not a bijection"
@@ -222,7 +229,9 @@ def replay_block(psi, w, n, R, mats, c64=False):
             w0 = int(w[op])
             kind, variant, k = w0 & 0xff, (w0 >> 8) & 0xff, (w0 >> 16) & 0xff
             moff = int(np.uint32(w[op + 1])) | (int(w[op + 2]) << 32)
-            if kind == 0:
+            if kind == 12:        # padding no-op
+                pass
+            elif kind == 0:
                 assert bin(variant).count("1") == k and variant < NR
                 D = 1 << k
                 M = mats[moff:moff + 2 * D * D].view(np.complex128).reshape(D, D)
