@@ -34,8 +34,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 PARAMS_PATH = os.path.join(_HERE, "data", "costmodel_params.npy")
 META_PATH = os.path.join(_HERE, "data", "costmodel_meta.json")
 
-# The geometry grid the learned planner searches (chunk C, register bits r,
-# low bits L, fusion width k); the harvest samples plans from the same grid.
+# The grid the learned planner searches (chunk C, register bits r, low bits L,
+# fusion width k, matrix cores for complex64, single-qubit gates split or
+# whole); the harvest samples plans from the same grid.
 GRID_C = (11, 12, 13)
 GRID_R = (3, 4, 5)
 GRID_L = (4, 5)
@@ -61,9 +62,10 @@ def suite(n, rng):
 
 
 def grid(dtype):
-    """(C, r, L, k, matrix cores) points the planner searches for this dtype."""
+    """(C, r, L, k, matrix cores, split) points the planner searches for this dtype."""
     mfs = (True, False) if dtype == "c64" else (True,)
-    return [(C, r, L, k, mf) for C in GRID_C for r in GRID_R for L in GRID_L for k in GRID_K for mf in mfs]
+    return [(C, r, L, k, mf, sp) for C in GRID_C for r in GRID_R for L in GRID_L for k in GRID_K for mf in mfs
+            for sp in (True, False)]
 
 
 def grid_options(rng, count, dtype="c128"):
@@ -74,14 +76,14 @@ def grid_options(rng, count, dtype="c128"):
 
 
 def opt_name(opt):
-    return "heur" if opt is None else "C%dr%dL%dk%d%s" % (opt[:4] + ("" if opt[4] else "v",))
+    return "heur" if opt is None else "C%dr%dL%dk%d%s%s" % (opt[:4] + ("" if opt[4] else "v", "" if opt[5] else "w"))
 
 
 def _plan(circ, opt, dtype):
     if opt is None:
         return qs.Plan(circ, kmax=5, dtype=dtype)
-    C, r, L, k, mf = opt
-    return qs.Plan(circ, kmax=k, dtype=dtype, chunk_qubits=C, reg_qubits=r, low_qubits=L, mfma=mf)
+    C, r, L, k, mf, sp = opt
+    return qs.Plan(circ, kmax=k, dtype=dtype, chunk_qubits=C, reg_qubits=r, low_qubits=L, mfma=mf, split=sp)
 
 
 def harvest(sizes=(26, 27, 28, 29, 30, 32), opts_per=(8, 8, 8, 6, 5, 2), dtypes=("c128",), seed=2406,

@@ -250,21 +250,27 @@ qs_status build_plan_search(const qs_circuit *c, int kmax, const qs_plan_opts *o
     for (int k = std::max(1, kmax - 3); k <= kmax; ++k) ks.push_back(k);
     std::vector<int> mfs{base.no_mfma};
     if (base.dtype == QS_C64 && !base.no_mfma) mfs.push_back(1);     // matrix cores on and off
+    // block contents too: single-qubit gates split (phase, shear rotation, phase) or kept
+    // whole (grouped 2x2 products, which also fuse into wider dense ops)
+    std::vector<int> sps{base.no_split};
+    if (!base.no_split && base.enable_fusion) sps.push_back(1);
     std::vector<Candidate> cands;
     for (int C : Cs)
         for (int r : rs)
             for (int L : Ls)
                 for (int k : ks)
-                    for (int nm : mfs) {
-                        Candidate cd;
-                        cd.o = base;
-                        cd.o.chunk_qubits = C;
-                        cd.o.reg_qubits = r;
-                        cd.o.low_qubits = L;
-                        cd.o.no_mfma = nm;
-                        cd.kmax = k;
-                        cands.push_back(std::move(cd));
-                    }
+                    for (int nm : mfs)
+                        for (int ns : sps) {
+                            Candidate cd;
+                            cd.o = base;
+                            cd.o.chunk_qubits = C;
+                            cd.o.reg_qubits = r;
+                            cd.o.low_qubits = L;
+                            cd.o.no_mfma = nm;
+                            cd.o.no_split = ns;
+                            cd.kmax = k;
+                            cands.push_back(std::move(cd));
+                        }
     // candidate plans are independent: build them on a few host threads
     const int nthr = (int)std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
     std::vector<std::thread> pool;
@@ -283,11 +289,12 @@ qs_status build_plan_search(const qs_circuit *c, int kmax, const qs_plan_opts *o
     for (auto &th : pool) th.join();
     // keep valid, distinct geometries (the planner may widen r or clip C and L)
     std::vector<Candidate *> keep{&heur};
-    std::vector<std::array<int, 5>> seen{
-        {heur.plan->C, heur.plan->r, heur.plan->L, std::min(kmax, heur.plan->r), heur.plan->mfma ? 1 : 0}};
+    std::vector<std::array<int, 6>> seen{{heur.plan->C, heur.plan->r, heur.plan->L, std::min(kmax, heur.plan->r),
+                                          heur.plan->mfma ? 1 : 0, base.no_split}};
     for (Candidate &cd : cands) {
         if (cd.rc) continue;
-        std::array<int, 5> sig{cd.plan->C, cd.plan->r, cd.plan->L, std::min(cd.kmax, cd.plan->r), cd.plan->mfma ? 1 : 0};
+        std::array<int, 6> sig{cd.plan->C, cd.plan->r, cd.plan->L, std::min(cd.kmax, cd.plan->r), cd.plan->mfma ? 1 : 0,
+                               cd.o.no_split};
         if (std::find(seen.begin(), seen.end(), sig) != seen.end()) continue;
         seen.push_back(sig);
         keep.push_back(&cd);
