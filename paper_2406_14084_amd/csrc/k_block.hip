@@ -141,10 +141,11 @@ __device__ __forceinline__ void multi1_dispatch(int mask, V (&v)[1 << R], P M)
 }
 #undef QS_MULTI_CASE
 
-// Real plane rotation on each register bit of MASK (ascending), as three shears
-// per amplitude pair (x0, x1) = (bit clear, bit set): x0 += a x1, x1 += b x0,
-// x0 += a x1, on the real and imaginary parts alike -- in place, one FMA each.
-// Coefficients (a, b) of the bits back to back.
+// Real plane rotation on each register bit of MASK (ascending), as two shears per
+// amplitude pair (x0, x1) = (bit clear, bit set): x0 += beta x1, then x1 += alpha x0,
+// on the real and imaginary parts alike -- in place, one FMA each.  (The rotation's
+// diagonal scaling, diag(cos, 1 / cos), is folded into the diagonal op before it.)
+// Coefficients (beta, alpha) of the bits back to back.
 __device__ __forceinline__ double fma_f(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fma_f(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
@@ -153,18 +154,16 @@ __device__ __forceinline__ void apply_rot_from(V (&v)[1 << R], P M)
 {
     if constexpr (J < R) {
         if constexpr ((MASK >> J) & 1) {
-            const F a = M[0], b = M[1];
+            const F beta = M[0], alpha = M[1];
 #pragma unroll
             for (int base = 0; base < (1 << R); ++base) {
                 if (base & (1 << J)) continue;
                 V &x0 = v[base];
                 V &x1 = v[base | (1 << J)];
-                x0.x = fma_f(a, x1.x, x0.x);
-                x0.y = fma_f(a, x1.y, x0.y);
-                x1.x = fma_f(b, x0.x, x1.x);
-                x1.y = fma_f(b, x0.y, x1.y);
-                x0.x = fma_f(a, x1.x, x0.x);
-                x0.y = fma_f(a, x1.y, x0.y);
+                x0.x = fma_f(beta, x1.x, x0.x);
+                x0.y = fma_f(beta, x1.y, x0.y);
+                x1.x = fma_f(alpha, x0.x, x1.x);
+                x1.y = fma_f(alpha, x0.y, x1.y);
             }
             apply_rot_from<R, MASK, J + 1, F, V, P>(v, M + 2);
         } else {
@@ -197,7 +196,8 @@ __device__ __forceinline__ void rot_dispatch(int mask, V (&v)[1 << R], P M)
 #undef QS_ROT_CASE
 
 // Permutation op (multi-controlled X: X, CX, CCX): flip register bit T of every
-// register whose bits in ctrl (uniform, bit T clear) are all set.  No
+// register whose bits in ctrl (uniform, bit T clear) equal cval (a control may
+// require 1 or 0).  No
 // arithmetic: each pair (m, m | 1 << T) swaps its bit patterns under a uniform
 // mask.  (A switch over every (target, controls) pattern with compile-time
 // moves, or selects between the pair, make the compiler index the register
@@ -220,13 +220,13 @@ __device__ __forceinline__ void cswap(float &a, float &b, uint64_t k)
 }
 
 template <int R, int T, typename V>
-__device__ __forceinline__ void apply_mcx(V (&v)[1 << R], uint32_t ctrl)
+__device__ __forceinline__ void apply_mcx(V (&v)[1 << R], uint32_t ctrl, uint32_t cval)
 {
 #pragma unroll
     for (int m = 0; m < (1 << R); ++m) {
         if ((m >> T) & 1) continue;
-        // all ones where register m's control bits are set (uniform, a scalar value)
-        const uint64_t k = 0ull - (uint64_t)(((uint32_t)m & ctrl) == ctrl);
+        // all ones where register m's control bits hold cval (uniform, a scalar value)
+        const uint64_t k = 0ull - (uint64_t)(((uint32_t)m & ctrl) == cval);
         cswap(v[m].x, v[m | (1 << T)].x, k);
         cswap(v[m].y, v[m | (1 << T)].y, k);
         // opaque to the optimiser: the cases of the dispatch switch must not be
@@ -236,15 +236,15 @@ __device__ __forceinline__ void apply_mcx(V (&v)[1 << R], uint32_t ctrl)
 }
 
 template <int R, typename V>
-__device__ __forceinline__ void mcx_dispatch(int var, V (&v)[1 << R])
+__device__ __forceinline__ void mcx_dispatch(int var, uint32_t cval, V (&v)[1 << R])
 {
     const uint32_t ctrl = (uint32_t)var >> 3;
     switch (var & 7) {
-    case 0: apply_mcx<R, 0, V>(v, ctrl); break;
-    case 1: if constexpr (R > 1) apply_mcx<R, (R > 1 ? 1 : 0), V>(v, ctrl); else __builtin_unreachable(); break;
-    case 2: if constexpr (R > 2) apply_mcx<R, (R > 2 ? 2 : 0), V>(v, ctrl); else __builtin_unreachable(); break;
-    case 3: if constexpr (R > 3) apply_mcx<R, (R > 3 ? 3 : 0), V>(v, ctrl); else __builtin_unreachable(); break;
-    case 4: if constexpr (R > 4) apply_mcx<R, (R > 4 ? 4 : 0), V>(v, ctrl); else __builtin_unreachable(); break;
+    case 0: apply_mcx<R, 0, V>(v, ctrl, cval); break;
+    case 1: if constexpr (R > 1) apply_mcx<R, (R > 1 ? 1 : 0), V>(v, ctrl, cval); else __builtin_unreachable(); break;
+    case 2: if constexpr (R > 2) apply_mcx<R, (R > 2 ? 2 : 0), V>(v, ctrl, cval); else __builtin_unreachable(); break;
+    case 3: if constexpr (R > 3) apply_mcx<R, (R > 3 ? 3 : 0), V>(v, ctrl, cval); else __builtin_unreachable(); break;
+    case 4: if constexpr (R > 4) apply_mcx<R, (R > 4 ? 4 : 0), V>(v, ctrl, cval); else __builtin_unreachable(); break;
     default: __builtin_unreachable();
     }
 }
@@ -439,13 +439,15 @@ __device__ __forceinline__ void load_regs(V (&v)[1 << R], const V *__restrict__ 
     for (int m = 0; m < (1 << R); ++m) v[m] = amps[g | o[m]];
 }
 
+// g: the thread's part of the addresses, XOR the store's inversion mask (which may
+// cover register positions too, hence XOR with the register offsets)
 template <int R, typename V>
 __device__ __forceinline__ void store_regs(const V (&v)[1 << R], V *__restrict__ amps, uint64_t g, const int (&pos)[R])
 {
     uint64_t o[1 << R];
     reg_offsets<R>(o, pos);
 #pragma unroll
-    for (int m = 0; m < (1 << R); ++m) amps[g | o[m]] = v[m];
+    for (int m = 0; m < (1 << R); ++m) amps[g ^ o[m]] = v[m];
 }
 
 // Chunk base: the chunk index spread over the physical qubits outside the chunk.
@@ -500,17 +502,10 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
     for (int b = 0; b < C; ++b) cmask |= 1ull << Pin[b];
 
     // per-lane data of diagonal ops: staged once into LDS, after the exchange buffer
-    // (half the chunk when every exchange of the block runs in two rounds)
+    // (half the chunk when every exchange of the block runs in two rounds); filled
+    // below, after the chunk's loads are issued, so the two latencies overlap
     const bool half = (flags & 4) != 0;
     int *ltab = reinterpret_cast<int *>(lds_raw + ((size_t)sizeof(V) << (half ? C - 1 : C)));
-    {
-        const int tab_off = prog[4], tab_words = prog[5];
-        for (int i = (int)tid; i < tab_words; i += (int)blockDim.x) ltab[i] = prog[tab_off + i];
-        if (tab_words) {
-            __builtin_amdgcn_s_waitcnt(0);
-            __builtin_amdgcn_s_barrier();
-        }
-    }
 
     // last phase (its layout is the store layout)
     const int *phl = ph0;
@@ -538,6 +533,38 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
     {
         V v[NR];
         load_regs<R>(v, amps, chunk_base(c, cmask, n) | gin_t, bin);
+        {
+            // the table, four words per thread in flight per round trip (sixteen for tables
+            // larger than four words per thread); the first round outside the loop (a loop
+            // header would wait for every load in flight, the chunk's included).  Indices are
+            // clamped into the table, so the loads need no per-lane branch; a group of words
+            // wholly past the table's end is skipped by a uniform test.
+            const int tab_off = prog[4], tab_words = prog[5];
+            const int nt = (int)blockDim.x;
+            auto stage = [&](int b0, auto kgroups) __attribute__((always_inline)) {
+                constexpr int K = decltype(kgroups)::value;
+                int t[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    if (K == 4 || b0 + k * nt < tab_words)
+                        t[k] = prog[tab_off + min(b0 + k * nt + (int)tid, tab_words - 1)];
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const int i = b0 + k * nt + (int)tid;
+                    if (i < tab_words) ltab[i] = t[k];
+                }
+            };
+            if (tab_words) {
+                if (tab_words <= 4 * nt) {
+                    stage(0, std::integral_constant<int, 4>());
+                } else {
+                    stage(0, std::integral_constant<int, 16>());
+                    for (int b0 = 16 * nt; b0 < tab_words; b0 += 16 * nt) stage(b0, std::integral_constant<int, 16>());
+                }
+                __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): the table writes are done
+                __builtin_amdgcn_s_barrier();
+            }
+        }
         if (hazard) {
             // the write-back permutes positions and no exchange orders loads before
             // stores: every wave must hold its part of the chunk before any store
@@ -653,7 +680,7 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
                     if constexpr (KMAX > 0) multi1_dispatch<R, F, V, const CF *>(variant, v, M);
                     else __builtin_unreachable();
                 } else if (kind == OP_MCX) {
-                    mcx_dispatch<R, V>(variant, v);
+                    mcx_dispatch<R, V>(variant, __builtin_amdgcn_readfirstlane((uint32_t)op[3]), v);
                 } else if (kind == OP_ROT || kind == OP_ROTD) {
                     // one copy of the rotation paths for both kinds (code size)
                     rot_dispatch<R, F, V, const CF *>(variant, v, M);
@@ -739,7 +766,8 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
             ph = op;
         }
         // ---- store in the last layout, through P_out
-        store_regs<R>(v, amps, chunk_base(c, cmask, n) | gout_t, bout);
+        const uint64_t inv = (uint64_t)(uint32_t)prog[6] | ((uint64_t)(uint32_t)prog[7] << 32);
+        store_regs<R>(v, amps, (chunk_base(c, cmask, n) | gout_t) ^ inv, bout);
     }
 }
 

@@ -84,12 +84,12 @@ void block_features(const Plan &p, std::vector<float> *out)
                 case OP_ROT:     // grouped like the single-qubit ops, at its own arithmetic
                     ++nmulti;
                     nmulti_g += popc((uint32_t)mask);
-                    flops += 6.0 * popc((uint32_t)mask);
+                    flops += 4.0 * popc((uint32_t)mask);
                     break;
                 case OP_ROTD:    // a rotation op and a register diagonal in one dispatch
                     ++nmulti;
                     nmulti_g += popc((uint32_t)mask);
-                    flops += 6.0 * popc((uint32_t)mask) + 6;
+                    flops += 4.0 * popc((uint32_t)mask) + 6;
                     ++ndiag_reg;
                     break;
                 case OP_DIAG_REG: ++ndiag_reg; flops += 6; diag_bits += k; break;

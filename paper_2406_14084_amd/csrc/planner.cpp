@@ -53,6 +53,17 @@ bool matrix_is_diag(const std::vector<cplx> &m, int d)
 
 int popc(uint32_t x) { return __builtin_popcount(x); }
 
+// X G X for X on the circuit index bits fl of the gate: every row and column index
+// XOR fl (a diagonal stays diagonal, a permutation a permutation).
+GateIn conjugate_x(const GateIn &G, uint32_t fl)
+{
+    GateIn r = G;
+    const int d = 1 << G.k;
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) r.m[(size_t)i * d + j] = G.m[(size_t)(i ^ fl) * d + (j ^ fl)];
+    return r;
+}
+
 // ---------------------------------------------------------------------------
 // Gate-block finding (Alg. 1 behaviour)
 // ---------------------------------------------------------------------------
@@ -153,10 +164,11 @@ struct SetOp {
     int perm = 0;                // permutation without arithmetic: 1 = multi-controlled X on bit ptarget (the
                                  // other bits of mask control), 2 = SWAP of the two bits of mask; m = its matrix
     int ptarget = -1;
+    uint32_t pcval = 0;          // perm 1: the values its controls must hold (local bits)
     bool pin = false;            // diagonal split off a single-qubit gate: runs only while its bits are in registers
     uint32_t mask = 0;           // local chunk bits
     std::vector<cplx> m;         // dense: d*d; diag: d
-    std::vector<std::array<double, 3>> rots;   // rot: (local bit, a, b) of the shears of each bit
+    std::vector<std::array<double, 3>> rots;   // rot: (local bit, beta, alpha) of the shears of each bit
     std::vector<int> gate_ids;
 };
 
@@ -246,47 +258,62 @@ double op_cost(bool diag, int k, bool mfma = false)
     if (mfma && k >= 4) return 2.0 * (double)(1 << k) + 8.0;
     return 4.0 * (double)(1 << k);
 }
-// a real rotation by three shears: three FMAs per amplitude (real and imaginary parts)
-constexpr double kRotCost = 3.0;
+// a real rotation by two shears: two FMAs per amplitude (real and imaginary parts)
+constexpr double kRotCost = 2.0;
 // a permutation op: register moves only
 constexpr double kPermCost = 0.25;
 
-// Single-qubit gate as diag(p) * Rot(theta) * diag(q), Rot = [[c, -s], [s, c]] with
-// c = cos theta, s = sin theta, theta in [0, pi/2] (the phases absorb every sign).
-// For a unitary U: c = |u00|, s = |u10|, q = (1, q1), p0 q0 = u00 / c, p1 q0 = u10 / s,
-// -p0 s q1 = u01.  The rotation runs as three shears (a = -tan(theta/2), b = sin theta):
-//     [[1, a], [0, 1]] [[1, 0], [b, 1]] [[1, a], [0, 1]] = Rot(theta)
-// (1 + ab = cos theta, a (2 + ab) = -sin theta), each shear one FMA per real component,
-// in place, coefficients of magnitude <= 1.  Accepted only when the product of the
-// factors reproduces U to 1e-14 (a non-unitary matrix stays a dense gate); diagonal
-// gates (s = 0) never come here.
-bool split_rotation(const std::vector<cplx> &u, cplx *pre, cplx *post, double *a, double *b, std::vector<cplx> *rot)
+// Single-qubit gate U as diag(p) * Rot(theta) * diag(q), Rot = [[c, -s], [s, c]],
+// c = cos theta, s = sin theta, theta in [0, pi/2] (the phases absorb every sign):
+// c = |u00|, s = |u10|, q = (1, q1), p0 = u00 / c, p1 = u10 / s, q1 = -u01 / (p0 s).
+// The rotation runs as two shears after a scaling that joins the phase before it:
+//     Rot(theta) = [[1, 0], [t, 1]] [[1, -s c], [0, 1]] diag(c, 1 / c),   t = s / c,
+// i.e. x0 += (-s c) x1, then x1 += t x0, each one FMA per real component, in place.
+// 1 / c stays small only for theta <= pi/4; for a larger angle the gate is taken as
+// X * U' with U' = X U (rows swapped, angle pi/2 - theta) and the X is left pending:
+// the caller carries it forward (later gates on the bit are conjugated by X; the chunk
+// is stored with the bit inverted), so every rotation has c >= 1/sqrt 2, t <= 1 and
+// s c <= 1/2.  Outputs: pre = q scaled by (c, 1/c), post = p, (beta, alpha) = (-s c, t),
+// *rot = the matrix of the two shears, *flip = whether the X is pending.  Accepted only
+// when the factors reproduce U to 1e-14 (a non-unitary matrix stays a dense gate);
+// diagonal gates (s = 0) never come here.
+bool split_rotation(const std::vector<cplx> &u_in, cplx *pre, cplx *post, double *beta, double *alpha,
+                    std::vector<cplx> *rot, bool *flip)
 {
-    const cplx u00 = u[0], u01 = u[1], u10 = u[2], u11 = u[3];
+    std::vector<cplx> u = u_in;
+    *flip = std::abs(u_in[2]) > std::abs(u_in[0]);
+    if (*flip) u = {u_in[2], u_in[3], u_in[0], u_in[1]};
+    const cplx u00 = u[0], u01 = u[1], u10 = u[2];
     const double theta = std::atan2(std::abs(u10), std::abs(u00));
     const double c = std::cos(theta), s = std::sin(theta);
     if (!(s > 1e-6)) return false;
-    const cplx p0 = std::abs(u00) > 0 ? u00 / std::abs(u00) : cplx(1, 0);
+    const cplx p0 = u00 / std::abs(u00);
     const cplx p1 = u10 / std::abs(u10);
     const cplx q1 = -u01 * std::conj(p0) / s;
     if (std::abs(std::abs(q1) - 1.0) > 1e-14) return false;
-    const cplx rec[4] = {p0 * c, -p0 * s * q1, p1 * s, p1 * c * q1};
-    for (int i = 0; i < 4; ++i)
-        if (std::abs(rec[i] - u[i]) > 1e-14) return false;
-    (void)u11;
-    pre[0] = cplx(1, 0);
-    pre[1] = q1;
+    const double t = s / c, b = -s * c;
+    // shears times scaling: [[c, b / c], [t c, (t b + 1) / c]] = [[c, -s], [s, c]]
+    const cplx shear[4] = {cplx(1, 0), cplx(b, 0), cplx(t, 0), cplx(t * b + 1.0, 0)};
+    const cplx sc[2] = {cplx(c, 0), q1 / c};
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            const cplx rec = (i ? p1 : p0) * shear[2 * i + j] * sc[j];
+            if (std::abs(rec - u[2 * i + j]) > 1e-14) return false;
+        }
+    pre[0] = sc[0];
+    pre[1] = sc[1];
     post[0] = p0;
     post[1] = p1;
-    *a = -std::tan(0.5 * theta);
-    *b = s;
-    *rot = {cplx(c, 0), cplx(-s, 0), cplx(s, 0), cplx(c, 0)};
+    *beta = b;
+    *alpha = t;
+    *rot = {shear[0], shear[1], shear[2], shear[3]};
     return true;
 }
 
 // A dense set op whose matrix is exactly a multi-controlled X (X, CX, CCX: flip one
-// bit where every other bit of the op is 1) or a SWAP of its two bits becomes a
-// permutation op: the kernel moves registers and does no arithmetic.
+// bit where every other bit of the op holds a given value, 1 or 0 per control) or a
+// SWAP of its two bits becomes a permutation op: the kernel moves registers and does
+// no arithmetic.
 void classify_perm(SetOp *s)
 {
     const int k = popc(s->mask), d = 1 << k;
@@ -299,10 +326,14 @@ void classify_perm(SetOp *s)
     };
     for (int t = 0; t < k; ++t) {
         const int ctrl = (d - 1) & ~(1 << t);
-        if (matches([&](int c) { return (c & ctrl) == ctrl ? c ^ (1 << t) : c; })) {
-            s->perm = 1;
-            s->ptarget = __builtin_ctz(pdep(1 << t, s->mask));
-            return;
+        for (int cv = ctrl;; cv = (cv - 1) & ctrl) {    // control values, all-ones first
+            if (matches([&](int c) { return (c & ctrl) == cv ? c ^ (1 << t) : c; })) {
+                s->perm = 1;
+                s->ptarget = __builtin_ctz(pdep(1 << t, s->mask));
+                s->pcval = pdep(cv, s->mask);
+                return;
+            }
+            if (cv == 0) break;
         }
     }
     if (k == 2 && matches([](int c) { return ((c & 1) << 1) | ((c >> 1) & 1); })) s->perm = 2;
@@ -486,7 +517,7 @@ struct PhaseSched {
         for (int u = 0; u < (1 << k); ++u) {
             uint32_t x = pdep(u, r.mask), y = x;
             if (pm.perm == 1) {
-                if ((x & ctrl) == ctrl) y ^= 1u << pm.ptarget;
+                if ((x & ctrl) == pm.pcval) y ^= 1u << pm.ptarget;
             } else {
                 const int a = __builtin_ctz(pm.mask), b = 31 - __builtin_clz(pm.mask);
                 const uint32_t ba = (x >> a) & 1, bb = (x >> b) & 1;
@@ -683,6 +714,7 @@ Op to_kernel_op(const SetOp &s, const Layout &lay, int r)
         for (int j = 0; j < r; ++j) {
             if (s.mask >> lay.R[j] & 1) mask |= 1 << j;
             if (s.perm == 1 && lay.R[j] == s.ptarget) op.ptarget = j;
+            if (s.perm == 1 && (s.pcval >> lay.R[j] & 1)) op.pcval |= 1 << j;
         }
         op.regmask = mask;
         if (popc((uint32_t)mask) != op.k || (s.perm == 1 && op.ptarget < 0))
@@ -690,7 +722,7 @@ Op to_kernel_op(const SetOp &s, const Layout &lay, int r)
         return op;
     }
     if (s.rot) {
-        // coefficients (a, b) per register bit, ascending register index
+        // coefficients (beta, alpha) per register bit, ascending register index
         op.kind = OP_ROT;
         op.m.clear();
         int mask = 0;
@@ -1010,19 +1042,41 @@ qs_status build_plan(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan 
         p->layouts.push_back(l2p);
         // ops in local bits
         std::vector<SetOp> ops;
+        uint32_t flip = 0;
         for (int gi : take) {
             const GateIn &G = gates[gi];
             int loc[5];
             for (int j = 0; j < G.k; ++j) loc[j] = loc_of_phys[l2p[G.t[j]]];
             blk.gate_ids.push_back(gi);
+            // a SWAP carries pending X gates (see below) over to the other bit and stays a SWAP
+            if (split && G.k == 2 && ((flip >> loc[0]) ^ (flip >> loc[1])) & 1) {
+                static const cplx sw[16] = {1, 0, 0, 0, 0, 0, 1, 0, 0, 1, 0, 0, 0, 0, 0, 1};
+                if (std::equal(G.m.begin(), G.m.end(), sw)) {
+                    flip ^= (1u << loc[0]) | (1u << loc[1]);
+                    ops.push_back(gate_to_setop(G, loc, gi));
+                    continue;
+                }
+            }
+            // bits with an X pending: the gate acts on the state as X G X would on the
+            // stored amplitudes, so its matrix indices flip on those bits
+            uint32_t fl = 0;
+            for (int j = 0; j < G.k; ++j)
+                if (flip >> loc[j] & 1) fl |= 1u << (G.k - 1 - j);
+            const GateIn Gc = fl ? conjugate_x(G, fl) : G;
             cplx pre[2], post[2];
-            double ra, rb;
+            double rb, ra;
+            bool fx = false;
             std::vector<cplx> rm;
-            // (an X stays a permutation op: register moves instead of a rotation)
-            const bool is_x = G.k == 1 && G.m[0] == cplx(0, 0) && G.m[1] == cplx(1, 0) && G.m[2] == cplx(1, 0) &&
-                              G.m[3] == cplx(0, 0);
-            if (split && G.k == 1 && !G.diag && !is_x && split_rotation(G.m, pre, post, &ra, &rb, &rm)) {
-                // phase, rotation, phase: the phases merge with neighbouring diagonals
+            const bool is_x = Gc.k == 1 && Gc.m[0] == cplx(0, 0) && Gc.m[1] == cplx(1, 0) && Gc.m[2] == cplx(1, 0) &&
+                              Gc.m[3] == cplx(0, 0);
+            if (split && is_x) {
+                // an X only toggles its bit's pending flip: no op at all
+                flip ^= 1u << loc[0];
+                continue;
+            }
+            if (split && Gc.k == 1 && !Gc.diag && split_rotation(Gc.m, pre, post, &rb, &ra, &rm, &fx)) {
+                // phase (with the rotation's scaling), two shears, phase: the phases merge with
+                // neighbouring diagonals; a pending X (fx) goes on to the end of the block
                 SetOp d0, rt, d1;
                 d0.diag = d1.diag = true;
                 d0.pin = d1.pin = true;
@@ -1031,15 +1085,19 @@ qs_status build_plan(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan 
                 d1.m = {post[0], post[1]};
                 rt.rot = true;
                 rt.m = rm;
-                rt.rots.push_back({(double)loc[0], ra, rb});
+                rt.rots.push_back({(double)loc[0], rb, ra});
                 rt.gate_ids.push_back(gi);
                 ops.push_back(std::move(d0));
                 ops.push_back(std::move(rt));
                 ops.push_back(std::move(d1));
+                if (fx) flip ^= 1u << loc[0];
                 continue;
             }
-            ops.push_back(gate_to_setop(G, loc, gi));
+            ops.push_back(gate_to_setop(Gc, loc, gi));
         }
+        // X gates still pending on local bits: the store writes every amplitude with
+        // these bits of its local index inverted
+        blk.flip = flip;
         // ---- output placement (folded swap)
         std::vector<int> newpos(C);   // local bit b (logical p2l[P_in[b]]) -> physical
         for (int b = 0; b < C; ++b) newpos[b] = blk.P_in[b];
@@ -1147,6 +1205,7 @@ qs_status build_plan(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan 
                         Op x = k;
                         x.kind = OP_MCX;
                         x.ptarget = t;
+                        x.pcval = k.regmask & ~(1 << t);
                         kops.push_back(x);
                     }
                     continue;
@@ -1337,7 +1396,7 @@ qs_status build_plan(const qs_circuit *c, int kmax, const qs_plan_opts *o, Plan 
                 ++s.ops;
                 if (op.kind == OP_DIAG) { ++s.ops_diag; s.flops_per_amp += 6.0; }
                 else if (op.kind == OP_MULTI1) { s.ops_dense[1] += op.k; s.flops_per_amp += 16.0 * op.k; }
-                else if (op.kind == OP_ROT) { s.ops_rot += op.k; s.flops_per_amp += 6.0 * op.k; }
+                else if (op.kind == OP_ROT) { s.ops_rot += op.k; s.flops_per_amp += 4.0 * op.k; }
                 else if (op.kind == OP_MCX || op.kind == OP_SWAPR) ++s.ops_perm;
                 else {
                     ++s.ops_dense[op.k];
@@ -1452,7 +1511,10 @@ static void check_program(const Plan &p)
                 case OP_DENSE: ok = var > 0 && var < NR && __builtin_popcount(var) <= kw; break;
                 case OP_MULTI1: ok = kw >= 1 && var > 0 && var < NR; break;
                 case OP_ROT: case OP_ROTD: ok = var > 0 && var < NR; break;
-                case OP_MCX: ok = (var & 7) < r && (var >> 3) < NR && !(((var >> 3) >> (var & 7)) & 1); break;
+                case OP_MCX:
+                    ok = (var & 7) < r && (var >> 3) < NR && !(((var >> 3) >> (var & 7)) & 1) &&
+                         (op[3] & ~(var >> 3)) == 0;
+                    break;
                 case OP_MFMA:
                     ok = bm && r == 5 && (var == 15 || var == 23 || var == 27 || var == 29 || var == 30 || var == 31);
                     break;
@@ -1517,11 +1579,15 @@ void encode_plan(Plan *p)
                 }
             if (best < 0) half = false;
         }
-        w.push_back((blk.permute_only ? 1 : 0) | (blk.P_out != blk.P_in ? 2 : 0) | (half ? 4 : 0));
+        // the store inverts the pending-X bits: physical positions of those local bits
+        uint64_t fphys = 0;
+        for (int b = 0; b < C; ++b)
+            if (blk.flip >> b & 1) fphys |= 1ull << blk.P_out[b];
+        w.push_back((blk.permute_only ? 1 : 0) | (blk.P_out != blk.P_in || fphys ? 2 : 0) | (half ? 4 : 0));
         w.push_back(0);   // table offset, patched below
         w.push_back(0);   // table words
-        w.push_back(0);
-        w.push_back(0);
+        w.push_back((int32_t)(uint32_t)(fphys & 0xffffffffu));
+        w.push_back((int32_t)(uint32_t)(fphys >> 32));
         for (int b = 0; b < C; ++b) w.push_back(blk.P_in[b]);
         for (int b = 0; b < C; ++b) w.push_back(blk.P_out[b]);
         std::vector<int32_t> tab;   // per-lane data of diagonal ops, staged in LDS by the kernel
@@ -1683,7 +1749,7 @@ void encode_plan(Plan *p)
                     w.push_back(OP_MCX | (var << 8) | (op.k << 16));
                     w.push_back(0);
                     w.push_back(0);
-                    w.push_back(0);
+                    w.push_back(op.pcval);
                     continue;
                 }
                 if (op.kind == OP_DENSE || op.kind == OP_MULTI1 || op.kind == OP_ROT) {

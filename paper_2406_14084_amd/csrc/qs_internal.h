@@ -38,7 +38,8 @@ enum OpKind {
     OP_ROT = 8,        // a real plane rotation on each register bit of regmask, as three shears
                        // x0 += a x1, x1 += b x0, x0 += a x1 (coefficients (a, b) per bit, ascending)
     OP_MCX = 9,        // permutation, no arithmetic: flip register bit ptarget of every register whose
-                       // bits in regmask & ~(1 << ptarget) (the controls) are all set (X, CX, CCX)
+                       // bits in regmask & ~(1 << ptarget) (the controls) equal pcval (X, CX, CCX
+                       // with controls on 1 or 0)
     OP_SWAPR = 10,     // planner only: SWAP of the two register bits of regmask, encoded as three OP_MCX
     OP_ROTD = 11,      // encoding only: an OP_ROT followed by a diagonal on register bits, in one op
     OP_NOP = 12        // encoding only: pads a phase of a block without dense ops to an even op count
@@ -54,6 +55,7 @@ struct Op {
     // Diag:  local chunk bits tl[0..k-1] ascending; table index bit i <-> tl[i].
     int regmask = 0;
     int ptarget = -1;             // OP_MCX: register position of the flipped bit
+    int pcval = 0;                // OP_MCX: control values (register mask within the controls)
     int k = 0;
     int tl[kMaxDiagBits] = {0};
     std::vector<cplx> m;          // dense: (2^k)^2 row-major; diag: 2^k
@@ -76,6 +78,7 @@ struct Block {
     std::vector<Phase> phases;
     std::vector<int> gate_ids;    // original gates in execution order
     bool permute_only = false;    // a swap pass: no ops
+    uint32_t flip = 0;            // local bits with an X pending at the end: stored inverted
 };
 
 struct Plan {
@@ -117,7 +120,9 @@ qs_status build_plan_search(const qs_circuit *c, int kmax, const qs_plan_opts *o
 // Program encoding read by the blocked kernel (int32 words per block):
 //   [0] nphases, [1] C, [2] r, [3] flags (bit 0 swap pass, bit 1 P_out != P_in,
 //       bit 2 every exchange runs in two rounds through half the LDS buffer)
-//   [4] table offset (words from block start, multiple of 4), [5] table words, [6..8) 0
+//   [4] table offset (words from block start, multiple of 4), [5] table words,
+//   [6], [7] store inversion mask (physical bits, low / high word): the store writes the
+//       amplitude of index x at x ^ mask (pending X gates of the block)
 //   [8 .. 8+C)        P_in
 //   [8+C .. 8+2C)     P_out
 //   then per phase:
@@ -148,9 +153,11 @@ qs_status build_plan_search(const qs_circuit *c, int kmax, const qs_plan_opts *o
 //                 matrix in matrix-core operand order (complex64 only)
 //       SIGN_REG: w3 = mask over registers (bit m set: negate register m)
 //       SIGN_ROW: w1 = tmask; w3 = word offset in the table of 2^kt row masks
-//       ROT     : variant = register mask; w1,w2 = offset of (a, b) per set bit, ascending
-//       MCX     : variant = target register position (bits 0-2) | control register mask << 3
-//       ROTD    : variant = register mask; w1,w2 = offset of (a, b) per set bit, ascending, then
+//       ROT     : variant = register mask; w1,w2 = offset of (beta, alpha) per set bit,
+//                 ascending: x0 += beta x1, then x1 += alpha x0 on each pair
+//       MCX     : variant = target register position (bits 0-2) | control register mask << 3;
+//                 w3 = the values the controls must hold (register mask, within the controls)
+//       ROTD    : variant = register mask; w1,w2 = offset of (beta, alpha) per set bit, ascending, then
 //                 the 2^r entries of a diagonal in register order (applied after the shears)
 //       (blocks without dense ops hold an even op count per phase; an OP_NOP pads)
 // The table (per-lane data of diagonal ops) is copied into LDS, after the

@@ -10,13 +10,20 @@ times the 2-norm of its input (the u term covers the single rounding of the
 matrix to FP32, the 2^(k/2) bounds the 2-norm of |U| for unitary U); a
 diagonal op costs eps_diag = sqrt(2) gamma_2 + u; a +-1 diagonal costs 0.
 A single-qubit gate split into phase * rotation * phase has two diagonal ops
-and one rotation run as three shears S_a S_b S_a (|a|, |b| <= 1, so every
-shear has 2-norm <= phi = (1 + sqrt 5) / 2): rounding a and b to FP32 moves
-the product by <= 3 phi^2 u, and each shear's single FMA rounding adds
-<= 3 sqrt(2) phi^2 u, so
-    eps_rot = 3 phi^2 (1 + sqrt 2) u (1 + 1e-4) + 2e-14
+and one rotation run as two shears after a scaling diag(c, 1/c) that joins the
+diagonal before it (c = cos theta >= 1/sqrt 2, shear coefficients |beta| <=
+1/2, |alpha| <= 1).  The shears undo the scaling exactly (S_alpha S_beta =
+Rot Lambda^-1), and every rounding error made while a component carries its
+scale factor is proportional to that component, so after the shears it
+counts at the unscaled size: the diagonal keeps its eps_diag.  For a pair
+(x0, x1) of norm rho: z0 = y0 + beta y1 has |z0| <= rho, its FMA rounding
+<= u rho and the rounding of beta <= |beta| u |y1| <= u rho / sqrt 2; z1 = y1 +
+alpha z0 takes z0's error times |alpha| <= 1, its own FMA rounding and the
+rounding of alpha, each <= u rho.  The pair's error is at most
+sqrt(1.71^2 + 3.71^2) u rho = 4.08 u rho, so
+    eps_rot = 4.08 u (1 + 1e-4) + 2e-14
 per rotated qubit (the last term covers the FP64 factorisation).  Errors of
-successive (near-)unitary ops add to first order:
+successive ops add to first order:
     ||psi_c64 - psi_exact||_2 <= sum over ops of eps_op,
 and max|delta amp| <= ||delta||_2, 1 - fidelity <= ||delta||_2^2.
 
@@ -34,8 +41,9 @@ the error's 2-norm is about u sqrt(rho / 3) ||x||.  rho per op kind:
              total), plus one rounding of each coefficient (1 in total):
              rho = 2^k + 1;
   diagonal:  one product and one FMA per component plus the coefficient: 3;
-  rotation:  three shears, each one FMA on one of the pair, amplified by at
-             most phi^2 through the later shears, plus the coefficients: 3 phi^2 + 2;
+  rotation:  two shears: z1 passes through its own FMA, alpha's rounding
+             and z0's two (FMA, beta) carried by |alpha| <= 1, z0 through
+             two: at most 4 per component;
   +-1 diagonal: exact, 0.
 Independent ops add in quadrature: typical = u sqrt(sum_ops rho_op / 3).  The
 tests assert measured <= TYPICAL_MULTIPLE * typical (and <= the rigorous
@@ -47,7 +55,6 @@ from __future__ import annotations
 import math
 
 U32 = 2.0 ** -24
-PHI = (1 + math.sqrt(5)) / 2
 TYPICAL_MULTIPLE = 10.0
 
 
@@ -60,10 +67,10 @@ def eps_dense(k):
 
 
 EPS_DIAG = math.sqrt(2) * gamma(2) + U32
-EPS_ROT = 3 * PHI ** 2 * (1 + math.sqrt(2)) * U32 * (1 + 1e-4) + 2e-14
+EPS_ROT = math.sqrt((1 + 1 / math.sqrt(2)) ** 2 + (3 + 1 / math.sqrt(2)) ** 2) * U32 * (1 + 1e-4) + 2e-14
 
 RHO_DIAG = 3.0
-RHO_ROT = 3 * PHI ** 2 + 2
+RHO_ROT = 4.0
 
 
 def rho_dense(k):

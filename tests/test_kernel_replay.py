@@ -244,10 +244,11 @@ def replay_block(psi, w, n, R, mats, c64=False):
                     res = np.einsum("rc,wtc->wtr", M, vin)
                     out[:, :, cols] = res
                 v = out
-            elif kind == 9:       # multi-controlled X: flip register bit t where the control bits are set
+            elif kind == 9:       # multi-controlled X: flip register bit t where the controls hold cval
                 t, ctrl = variant & 7, variant >> 3
-                assert t < R and ctrl < NR and not (ctrl >> t) & 1
-                src = np.array([m ^ (1 << t) if (m & ctrl) == ctrl else m for m in range(NR)])
+                cval = int(w[op + 3])
+                assert t < R and ctrl < NR and not (ctrl >> t) & 1 and (cval & ~ctrl) == 0
+                src = np.array([m ^ (1 << t) if (m & ctrl) == cval else m for m in range(NR)])
                 v = v[:, :, src]
             elif kind == 10:      # SWAP of register bits a < b
                 a, b = variant & 7, variant >> 3
@@ -269,20 +270,19 @@ def replay_block(psi, w, n, R, mats, c64=False):
                         out[:, :, cols] = np.einsum("rc,wtc->wtr", M, v[:, :, cols])
                     v = out
                     idx += 1
-            elif kind == 8 or kind == 11:  # real rotation per register bit (shears), ascending;
+            elif kind == 8 or kind == 11:  # two shears per register bit, ascending;
                 # kind 11: then a diagonal on the registers (2^R entries after the coefficients)
                 idx = 0
                 for j in range(R):
                     if not (variant >> j) & 1:
                         continue
-                    a, b = float(mats[moff + 2 * idx]), float(mats[moff + 2 * idx + 1])
-                    assert abs(a) <= 1 and abs(b) <= 1
+                    beta, alpha = float(mats[moff + 2 * idx]), float(mats[moff + 2 * idx + 1])
+                    assert abs(beta) <= 0.5 + 1e-15 and abs(alpha) <= 1 + 1e-15
                     lo = [m for m in range(NR) if not (m >> j) & 1]
                     hi = [m | (1 << j) for m in lo]
                     x0, x1 = v[:, :, lo].copy(), v[:, :, hi].copy()
-                    x0 = x0 + a * x1
-                    x1 = x1 + b * x0
-                    x0 = x0 + a * x1
+                    x0 = x0 + beta * x1
+                    x1 = x1 + alpha * x0
                     v = v.copy()
                     v[:, :, lo], v[:, :, hi] = x0, x1
                     idx += 1
@@ -333,7 +333,10 @@ def replay_block(psi, w, n, R, mats, c64=False):
         prev = ph
         ph = op
     Rb, T = layout(prev)
-    so = gidx(Rb, T, Pout)
+    # pending X gates: the store inverts these physical bits of every address
+    inv = (int(np.uint32(w[6])) | (int(np.uint32(w[7])) << 32))
+    assert inv & ~sum(1 << q for q in Pout) == 0
+    so = gidx(Rb, T, Pout) ^ inv
     assert so.min() >= 0 and so.max() < (1 << n)
     assert np.unique(so).size == so.size == (1 << n), "store is not a bijection"
     for i in range(nwg):   # each workgroup writes exactly what it read
@@ -343,7 +346,7 @@ def replay_block(psi, w, n, R, mats, c64=False):
     # asks the kernel for a barrier (flag bit 1).
     if nph == 1 and not (int(w[3]) & 2):
         assert np.array_equal(np.sort(so, axis=2), np.sort(li, axis=2)), "store/load race between threads"
-    if Pin != Pout:
+    if Pin != Pout or inv:
         assert int(w[3]) & 2
     out = psi.copy()
     out[so] = v
