@@ -14,8 +14,9 @@ was taken on the current kernel and planner sources), the gate-by-gate
 path's throughput on the same circuit, the CPU oracle timed on a bounded
 sample of the same workload, and the variants compared with the plain fused
 path: complex64 with matrix-core ops (32 qubits), 512 batched QAOA
-instances in one launch vs 512 launches, and (with --learned) the learned
-planner on a 33-qubit complex128 circuit.
+instances in one launch vs 512 launches, the 31-qubit headline circuits, the
+H-gate and Table I micro-benchmarks, and the learned planner against the
+tuned heuristic and the fewest-passes plan on a 33-qubit complex128 circuit.
 """
 from __future__ import annotations
 
@@ -380,7 +381,8 @@ def main():
     ap.add_argument("--no-split", action="store_true",
                     help="keep single-qubit gates whole (no phase * rotation * phase split)")
     ap.add_argument("--no-variants", action="store_true", help="skip the complex64 and batched-QAOA comparisons")
-    ap.add_argument("--learned", action="store_true", help="also compare the learned planner at 33 qubits (128 GiB)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-planner comparison at 33 qubits (128 GiB)")
     ap.add_argument("--no-micro", action="store_true", help="skip the H-gate sweep and Table I gate benchmark")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -518,7 +520,7 @@ def main():
     if not args.no_micro:
         out["micro"] = bench_micro(torch, I, qs)
         torch.cuda.empty_cache()
-    if args.learned:
+    if not args.no_learned:
         out["learned_planner_33q"] = bench_learned(torch, I, qs)
         torch.cuda.empty_cache()
 

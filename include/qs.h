@@ -297,10 +297,11 @@ typedef struct {
 typedef struct qs_batch qs_batch;
 
 /* Pack count instances into device tables and a task queue.  An instance of
- * at most 13 qubits (complex64; 12 for complex128) runs whole in one
- * workgroup's LDS; a larger one keeps its state (and one byte per amplitude
- * of cached cut values) in a workspace and is split into chunk tasks, two
- * passes per layer.  dtype: QS_C64 (complex64 state, FP64 reductions) or
+ * at most CB qubits runs whole in one workgroup's LDS; a larger one keeps its
+ * state (and one byte per amplitude of cached cut values) in a workspace and
+ * is split into chunk tasks of 2^CB amplitudes, two passes per layer.  CB is
+ * 13 for complex64 and 12 for complex128 until qs_batch_autotune picks
+ * between that and one less (the workspace covers both).  dtype: QS_C64 (complex64 state, FP64 reductions) or
  * QS_C128.  hip_stream: stream for all work.  workspace / ws_bytes:
  * caller-owned device memory of at least qs_batch_qaoa_workspace_size()
  * bytes (256-byte aligned) for those states, or NULL to let the batch
@@ -334,11 +335,13 @@ QS_API qs_status qs_batch_free(qs_batch *b);
  * then invalid).  Synchronises the stream. */
 QS_API qs_status qs_batch_error(qs_batch *b, int *err);
 
-/* Choose the launch shape (threads 256/512 x workgroups per CU, 5 shapes) and
- * the number of chunks per task of the large instances (2, 8, 32 or 128) by
- * timing all 20 combinations on the device for this batch; *chosen gets
- * shape + 5 * grouping, and the choice stays in force for later runs of this
- * batch (a captured graph is re-captured).  Synchronises. */
+/* Choose the launch shape (threads 256/512 x workgroups per CU, 5 shapes),
+ * the number of chunks per task of the large instances (2, 8, 32 or 128) and
+ * the LDS chunk size CB (12 or 13 qubits for complex64, 11 or 12 for
+ * complex128) by timing all 40 combinations on the device for this batch;
+ * *chosen gets shape + 5 * (grouping + 4 * chunk size index), and the choice
+ * stays in force for later runs of this batch (a captured graph is
+ * re-captured).  Synchronises. */
 QS_API qs_status qs_batch_autotune(qs_batch *b, int *chosen, double *best_ms);
 
 /* ---- learned cost model (48 -> 128 -> 128 -> 1, FP32) --------------------- */

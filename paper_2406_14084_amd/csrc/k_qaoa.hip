@@ -11,7 +11,8 @@
 //     leaves when the queue is empty;
 //   - an instance of at most CB qubits is one task: its whole state lives in
 //     LDS (2^CB amplitudes), C(z) is tabulated once in LDS and reused by every
-//     layer and by the final reduction;
+//     layer and by the final reduction (CB, the launch shape and the chunks
+//     per task are chosen by timing them on the device: qs_batch_autotune);
 //   - a larger instance keeps its state in a workspace in HBM and is split
 //     into chunk tasks of 2^CB amplitudes per pass (two passes per layer: the
 //     low CB qubits, then the remaining high ones with a few low ones); a pass
@@ -52,6 +53,12 @@ constexpr unsigned kSpinLimit = 1u << 24;   // ~1 s of polling before giving up 
 constexpr int kGroups[] = {2, 8, 32, 128};
 constexpr int kNumGroups = 4;
 constexpr int kDefaultGroup = 1;
+// LDS chunk sizes (qubits) the autotuner tries, per dtype: the larger keeps more
+// instances whole in LDS, the smaller lets twice the workgroups share a CU (an
+// instance above the smaller size keeps its state in the workspace under it)
+constexpr int kNumCB = 2;
+constexpr int kDefaultCB = 1;
+constexpr int kCB64[kNumCB] = {12, 13}, kCB128[kNumCB] = {11, 12};
 
 template <typename F, typename V>
 __device__ __forceinline__ void rx_pair(V &a0, V &a1, F c, F s)
@@ -313,17 +320,21 @@ struct qs_batch {
     qs_dtype dtype = QS_C64;
     hipStream_t stream = nullptr;
     int device = 0;
-    void *d_inst = nullptr, *d_tasks = nullptr, *d_seq_tasks = nullptr, *d_edges = nullptr, *d_tab = nullptr;
+    // per LDS chunk size (kNumCB of them): descriptors (which instances are "large" and
+    // where their states sit depends on it), the batched queues and the sequential ones
+    void *d_inst[qs::kNumCB] = {nullptr}, *d_tasks[qs::kNumCB] = {nullptr}, *d_seq_tasks[qs::kNumCB] = {nullptr};
+    void *d_edges = nullptr, *d_tab = nullptr;
     void *d_work = nullptr, *d_ctr = nullptr;
     void *d_czw = nullptr;   // C(z) bytes of the large instances
     bool own_work = true;    // d_work / d_czw allocated by the batch (no caller workspace)
     int ntasks = 0;
-    std::vector<int> seq_begin, seq_count;   // per instance: its tasks in d_seq_tasks
+    std::vector<int> seq_begin[qs::kNumCB], seq_count[qs::kNumCB];   // per instance: its tasks in d_seq_tasks
     int nctr = 0;                            // [0] next, [1] err, [2..2+count) done, then one "next" per sequential launch
     int threads = 256;                       // autotuned
     int grid_per_cu = 2;                     // autotuned
     int group = qs::kDefaultGroup;           // autotuned: index into the chunk groupings
-    int grp_begin[qs::kNumGroups] = {0}, grp_count[qs::kNumGroups] = {0};
+    int cbi = qs::kDefaultCB;               // autotuned: index into the LDS chunk sizes
+    int grp_begin[qs::kNumCB][qs::kNumGroups] = {{0}}, grp_count[qs::kNumCB][qs::kNumGroups] = {{0}};
     int cus = 256;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -337,17 +348,16 @@ struct qs_batch {
 
 namespace {
 
-constexpr int kCB64 = 13, kCB128 = 12;
+int chunk_bits(qs_dtype dtype, int cbi) { return dtype == QS_C64 ? qs::kCB64[cbi] : qs::kCB128[cbi]; }
 
-template <typename F>
-hipError_t launch_qaoa(qs_batch *b, const void *tasks, int begin, int ntasks, unsigned *next, double *out, int threads,
-                       int grid)
+template <int CB, typename F>
+hipError_t launch_qaoa_cb(qs_batch *b, int cbi, const void *tasks, int begin, int ntasks, unsigned *next, double *out,
+                          int threads, int grid)
 {
     using namespace qs;
     using V = typename AmpOf<F>::type;
-    constexpr int CB = sizeof(F) == 4 ? kCB64 : kCB128;
     unsigned *ctr = reinterpret_cast<unsigned *>(b->d_ctr);
-    const QInst *I = reinterpret_cast<const QInst *>(b->d_inst);
+    const QInst *I = reinterpret_cast<const QInst *>(b->d_inst[cbi]);
     const QTask *T = reinterpret_cast<const QTask *>(tasks);
     const int2 *E = reinterpret_cast<const int2 *>(b->d_edges);
     const F *tab = reinterpret_cast<const F *>(b->d_tab);
@@ -362,7 +372,19 @@ hipError_t launch_qaoa(qs_batch *b, const void *tasks, int begin, int ntasks, un
     return hipGetLastError();
 }
 
-hipError_t run_batch(qs_batch *b, double *out, int threads, int grid_per_cu, int group)
+template <typename F>
+hipError_t launch_qaoa(qs_batch *b, int cbi, bool seq, int begin, int ntasks, unsigned *next, double *out, int threads,
+                       int grid)
+{
+    using namespace qs;
+    const void *tasks = seq ? b->d_seq_tasks[cbi] : b->d_tasks[cbi];
+    constexpr bool c64 = sizeof(F) == 4;
+    if (cbi == 0)
+        return launch_qaoa_cb<c64 ? kCB64[0] : kCB128[0], F>(b, 0, tasks, begin, ntasks, next, out, threads, grid);
+    return launch_qaoa_cb<c64 ? kCB64[1] : kCB128[1], F>(b, 1, tasks, begin, ntasks, next, out, threads, grid);
+}
+
+hipError_t run_batch(qs_batch *b, double *out, int threads, int grid_per_cu, int group, int cbi)
 {
     using namespace qs;
     unsigned *ctr = reinterpret_cast<unsigned *>(b->d_ctr);
@@ -370,10 +392,10 @@ hipError_t run_batch(qs_batch *b, double *out, int threads, int grid_per_cu, int
     hipLaunchKernelGGL(k_qaoa_reset, dim3((nz + 255) / 256), dim3(256), 0, b->stream, ctr, 2 + b->count, out, b->count);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int nt = b->grp_count[group], t0 = b->grp_begin[group];
+    const int nt = b->grp_count[cbi][group], t0 = b->grp_begin[cbi][group];
     const int grid = std::max(1, std::min(nt, b->cus * grid_per_cu));
-    if (b->dtype == QS_C64) return launch_qaoa<float>(b, b->d_tasks, t0, nt, ctr, out, threads, grid);
-    return launch_qaoa<double>(b, b->d_tasks, t0, nt, ctr, out, threads, grid);
+    if (b->dtype == QS_C64) return launch_qaoa<float>(b, cbi, false, t0, nt, ctr, out, threads, grid);
+    return launch_qaoa<double>(b, cbi, false, t0, nt, ctr, out, threads, grid);
 }
 
 }  // namespace
@@ -389,7 +411,7 @@ qs_status check_instances(int count, const qs_qaoa_instance *inst, qs_dtype dtyp
     using namespace qs;
     if (count < 1 || !inst) { set_error(std::string(fn) + ": bad arguments"); return QS_EINVAL; }
     if (dtype != QS_C64 && dtype != QS_C128) { set_error(std::string(fn) + ": bad dtype"); return QS_EINVAL; }
-    const int CB = dtype == QS_C64 ? kCB64 : kCB128;
+    const int CB = chunk_bits(dtype, 0);      // the smallest chunk size decides the two-pass limit
     for (int i = 0; i < count; ++i) {
         const qs_qaoa_instance &q = inst[i];
         if (q.n < 2 || q.n > 20 || q.nedges < 0 || q.nedges > 64 || q.p < 1 || q.p > 64 || (q.nedges && !q.edges) ||
@@ -404,10 +426,11 @@ qs_status check_instances(int count, const qs_qaoa_instance *inst, qs_dtype dtyp
     return QS_OK;
 }
 
-// amplitudes of the instances that keep their state outside LDS
-long long work_amplitudes(int count, const qs_qaoa_instance *inst, qs_dtype dtype)
+// amplitudes of the instances that keep their state outside LDS under the chunk
+// size cbi (the smallest size, index 0, needs the most)
+long long work_amplitudes(int count, const qs_qaoa_instance *inst, qs_dtype dtype, int cbi = 0)
 {
-    const int CB = dtype == QS_C64 ? kCB64 : kCB128;
+    const int CB = chunk_bits(dtype, cbi);
     long long work = 0;
     for (int i = 0; i < count; ++i)
         if (inst[i].n > CB) work += 1ll << inst[i].n;
@@ -445,7 +468,6 @@ qs_status qs_batch_qaoa_create(int count, const qs_qaoa_instance *inst, qs_dtype
     if (!out) { set_error("qs_batch_qaoa_create: bad arguments"); return QS_EINVAL; }
     qs_status rc0 = check_instances(count, inst, dtype, "qs_batch_qaoa_create");
     if (rc0) return rc0;
-    const int CB = dtype == QS_C64 ? kCB64 : kCB128;
     const size_t abytes = dtype == QS_C64 ? 8 : 16;
     size_t cz_off = 0;
     const size_t need = work_bytes(work_amplitudes(count, inst, dtype), dtype, &cz_off);
@@ -469,21 +491,15 @@ qs_status qs_batch_qaoa_create(int count, const qs_qaoa_instance *inst, qs_dtype
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, b->device) == hipSuccess && prop.multiProcessorCount > 0) b->cus = prop.multiProcessorCount;
 
-    // descriptors, edges, tables (phase table per layer computed in FP64, rounded once)
-    std::vector<QInst> I(count);
+    // edges and tables (phase table per layer computed in FP64, rounded once)
     std::vector<int> E;
     std::vector<double> tab;
-    long long work = 0;
+    std::vector<int> edge_off(count), tab_off(count);
     for (int i = 0; i < count; ++i) {
         const qs_qaoa_instance &q = inst[i];
-        QInst &d = I[i];
-        d.n = q.n;
-        d.nedges = q.nedges;
-        d.p = q.p;
-        d.large = q.n > CB ? 1 : 0;
-        d.edge_off = (int)(E.size() / 2);
+        edge_off[i] = (int)(E.size() / 2);
         for (int e = 0; e < 2 * q.nedges; ++e) E.push_back(q.edges[e]);
-        d.tab_off = (int)tab.size();
+        tab_off[i] = (int)tab.size();
         for (int l = 0; l < q.p; ++l) {
             for (int c = 0; c <= q.nedges; ++c) {
                 tab.push_back(std::cos(q.gammas[l] * c));
@@ -492,54 +508,7 @@ qs_status qs_batch_qaoa_create(int count, const qs_qaoa_instance *inst, qs_dtype
             tab.push_back(std::cos(q.betas[l]));
             tab.push_back(std::sin(q.betas[l]));
         }
-        d.work_off = d.large ? work : 0;
-        d.cz_off = d.large ? work : 0;        // one byte per amplitude, same layout as the states
-        if (d.large) work += 1ll << q.n;
-        d.res = i;
-        d.pad = 0;
     }
-    // queue: passes of the large instances interleaved, independent small
-    // instances (largest first) spread between the passes
-    std::vector<int> large, small;
-    for (int i = 0; i < count; ++i) (I[i].large ? large : small).push_back(i);
-    auto by_n = [&](int a, int c) { return I[a].n > I[c].n || (I[a].n == I[c].n && a < c); };
-    std::sort(large.begin(), large.end(), by_n);
-    std::sort(small.begin(), small.end(), by_n);
-    int maxpass = 0;
-    for (int i : large) maxpass = std::max(maxpass, 2 * I[i].p);
-    // one queue per chunk grouping, back to back in d_tasks
-    std::vector<QTask> tasks;
-    for (int gi = 0; gi < kNumGroups; ++gi) {
-        b->grp_begin[gi] = (int)tasks.size();
-        size_t si = 0;
-        for (int s = 0; s < maxpass; ++s) {
-            for (int i : large) {
-                if (s >= 2 * I[i].p) continue;
-                const int nch = 1 << (I[i].n - CB), grp = std::min(kGroups[gi], nch);
-                for (int j = 0; j < nch; j += grp) tasks.push_back({i, s, j, grp});
-            }
-            const size_t take = (small.size() * (size_t)(s + 1)) / (size_t)maxpass;
-            for (; si < take; ++si) tasks.push_back({small[si], 0, 0, 0});
-        }
-        for (; si < small.size(); ++si) tasks.push_back({small[si], 0, 0, 0});
-        b->grp_count[gi] = (int)tasks.size() - b->grp_begin[gi];
-    }
-    b->ntasks = b->grp_count[kDefaultGroup];
-    // per-instance task lists for the sequential reference
-    std::vector<QTask> seq;
-    b->seq_begin.resize(count);
-    b->seq_count.resize(count);
-    for (int i = 0; i < count; ++i) {
-        b->seq_begin[i] = (int)seq.size();
-        if (I[i].large) {
-            for (int s = 0; s < 2 * I[i].p; ++s)
-                for (int j = 0; j < (1 << (I[i].n - CB)); ++j) seq.push_back({i, s, j, 1});
-        } else {
-            seq.push_back({i, 0, 0, 0});
-        }
-        b->seq_count[i] = (int)seq.size() - b->seq_begin[i];
-    }
-    b->nctr = 2 + count + count;
     qs_status rc = QS_OK;
     auto alloc = [&](void **p, size_t bytes, const void *src, const char *what) {
         if (rc) return;
@@ -547,9 +516,71 @@ qs_status qs_batch_qaoa_create(int count, const qs_qaoa_instance *inst, qs_dtype
         if (e == hipSuccess && src && bytes) e = hipMemcpy(*p, src, bytes, hipMemcpyHostToDevice);
         if (e != hipSuccess) rc = hip_fail(e, what);
     };
-    alloc(&b->d_inst, I.size() * sizeof(QInst), I.data(), "qs_batch_qaoa_create: descriptors");
-    alloc(&b->d_tasks, tasks.size() * sizeof(QTask), tasks.data(), "qs_batch_qaoa_create: tasks");
-    alloc(&b->d_seq_tasks, seq.size() * sizeof(QTask), seq.data(), "qs_batch_qaoa_create: tasks");
+    // per LDS chunk size: descriptors, the batched queues, the sequential queues
+    for (int cbi = 0; cbi < kNumCB; ++cbi) {
+        const int CB = chunk_bits(dtype, cbi);
+        std::vector<QInst> I(count);
+        long long work = 0;
+        for (int i = 0; i < count; ++i) {
+            const qs_qaoa_instance &q = inst[i];
+            QInst &d = I[i];
+            d.n = q.n;
+            d.nedges = q.nedges;
+            d.p = q.p;
+            d.large = q.n > CB ? 1 : 0;
+            d.edge_off = edge_off[i];
+            d.tab_off = tab_off[i];
+            d.work_off = d.large ? work : 0;
+            d.cz_off = d.large ? work : 0;        // one byte per amplitude, same layout as the states
+            if (d.large) work += 1ll << q.n;
+            d.res = i;
+            d.pad = 0;
+        }
+        // queue: passes of the large instances interleaved, independent small
+        // instances (largest first) spread between the passes
+        std::vector<int> large, small;
+        for (int i = 0; i < count; ++i) (I[i].large ? large : small).push_back(i);
+        auto by_n = [&](int a, int c) { return I[a].n > I[c].n || (I[a].n == I[c].n && a < c); };
+        std::sort(large.begin(), large.end(), by_n);
+        std::sort(small.begin(), small.end(), by_n);
+        int maxpass = 0;
+        for (int i : large) maxpass = std::max(maxpass, 2 * I[i].p);
+        // one queue per chunk grouping, back to back
+        std::vector<QTask> tasks;
+        for (int gi = 0; gi < kNumGroups; ++gi) {
+            b->grp_begin[cbi][gi] = (int)tasks.size();
+            size_t si = 0;
+            for (int st = 0; st < maxpass; ++st) {
+                for (int i : large) {
+                    if (st >= 2 * I[i].p) continue;
+                    const int nch = 1 << (I[i].n - CB), grp = std::min(kGroups[gi], nch);
+                    for (int j = 0; j < nch; j += grp) tasks.push_back({i, st, j, grp});
+                }
+                const size_t take = (small.size() * (size_t)(st + 1)) / (size_t)maxpass;
+                for (; si < take; ++si) tasks.push_back({small[si], 0, 0, 0});
+            }
+            for (; si < small.size(); ++si) tasks.push_back({small[si], 0, 0, 0});
+            b->grp_count[cbi][gi] = (int)tasks.size() - b->grp_begin[cbi][gi];
+        }
+        // per-instance task lists for the sequential reference
+        std::vector<QTask> seq;
+        b->seq_begin[cbi].resize(count);
+        b->seq_count[cbi].resize(count);
+        for (int i = 0; i < count; ++i) {
+            b->seq_begin[cbi][i] = (int)seq.size();
+            if (I[i].large) {
+                for (int st = 0; st < 2 * I[i].p; ++st)
+                    for (int j = 0; j < (1 << (I[i].n - CB)); ++j) seq.push_back({i, st, j, 1});
+            } else {
+                seq.push_back({i, 0, 0, 0});
+            }
+            b->seq_count[cbi][i] = (int)seq.size() - b->seq_begin[cbi][i];
+        }
+        alloc(&b->d_inst[cbi], I.size() * sizeof(QInst), I.data(), "qs_batch_qaoa_create: descriptors");
+        alloc(&b->d_tasks[cbi], tasks.size() * sizeof(QTask), tasks.data(), "qs_batch_qaoa_create: tasks");
+        alloc(&b->d_seq_tasks[cbi], seq.size() * sizeof(QTask), seq.data(), "qs_batch_qaoa_create: tasks");
+    }
+    b->ntasks = b->grp_count[b->cbi][kDefaultGroup];
     alloc(&b->d_edges, E.size() * sizeof(int), E.data(), "qs_batch_qaoa_create: edges");
     if (dtype == QS_C64) {
         std::vector<float> t32(tab.begin(), tab.end());
@@ -557,6 +588,9 @@ qs_status qs_batch_qaoa_create(int count, const qs_qaoa_instance *inst, qs_dtype
     } else {
         alloc(&b->d_tab, tab.size() * sizeof(double), tab.data(), "qs_batch_qaoa_create: tables");
     }
+    // the workspace is laid out for the smallest chunk size (the most large
+    // instances); a larger one uses a prefix of the same states and cut bytes
+    const long long work = work_amplitudes(count, inst, dtype);
     if (workspace) {
         b->own_work = false;
         b->d_work = need ? workspace : nullptr;
@@ -565,6 +599,7 @@ qs_status qs_batch_qaoa_create(int count, const qs_qaoa_instance *inst, qs_dtype
         alloc(&b->d_work, (size_t)work * abytes, nullptr, "qs_batch_qaoa_create: workspace");
         alloc(&b->d_czw, (size_t)std::max<long long>(work, 1), nullptr, "qs_batch_qaoa_create: cut workspace");
     }
+    b->nctr = 2 + count + count;
     alloc(&b->d_ctr, (size_t)b->nctr * sizeof(unsigned), nullptr, "qs_batch_qaoa_create: counters");
     if (rc) {
         qs_batch_free(b);
@@ -580,7 +615,7 @@ qs_status qs_batch_qaoa_run(qs_batch *b, double *out_dev, int use_graph)
     if (!b || !out_dev) { set_error("qs_batch_qaoa_run: null argument"); return QS_EINVAL; }
     (void)hipSetDevice(b->device);
     if (!use_graph) {
-        hipError_t e = run_batch(b, out_dev, b->threads, b->grid_per_cu, b->group);
+        hipError_t e = run_batch(b, out_dev, b->threads, b->grid_per_cu, b->group, b->cbi);
         if (e != hipSuccess) return hip_fail(e, "qs_batch_qaoa_run");
         return QS_OK;
     }
@@ -596,7 +631,7 @@ qs_status qs_batch_qaoa_run(qs_batch *b, double *out_dev, int use_graph)
         hipStream_t user = b->stream;
         b->stream = b->gstream;
         hipError_t e = hipStreamBeginCapture(b->gstream, hipStreamCaptureModeThreadLocal);
-        hipError_t e2 = (e == hipSuccess) ? run_batch(b, out_dev, b->threads, b->grid_per_cu, b->group) : hipSuccess;
+        hipError_t e2 = (e == hipSuccess) ? run_batch(b, out_dev, b->threads, b->grid_per_cu, b->group, b->cbi) : hipSuccess;
         hipError_t e3 = (e == hipSuccess) ? hipStreamEndCapture(b->gstream, &b->graph) : hipSuccess;
         b->stream = user;
         if (e != hipSuccess) return hip_fail(e, "qs_batch_qaoa_run: begin capture");
@@ -623,13 +658,15 @@ qs_status qs_batch_qaoa_run_sequential(qs_batch *b, double *out_dev)
     unsigned *ctr = reinterpret_cast<unsigned *>(b->d_ctr);
     hipLaunchKernelGGL(k_qaoa_reset, dim3((b->nctr + 255) / 256), dim3(256), 0, b->stream, ctr, b->nctr, out_dev, b->count);
     hipError_t e = hipGetLastError();
+    const int cbi = b->cbi;
     for (int i = 0; i < b->count && e == hipSuccess; ++i) {
         unsigned *next = ctr + 2 + b->count + i;     // one queue counter per launch
-        const int grid = std::max(1, std::min(b->seq_count[i], b->cus * b->grid_per_cu));
+        const int nt = b->seq_count[cbi][i], t0 = b->seq_begin[cbi][i];
+        const int grid = std::max(1, std::min(nt, b->cus * b->grid_per_cu));
         if (b->dtype == QS_C64)
-            e = launch_qaoa<float>(b, b->d_seq_tasks, b->seq_begin[i], b->seq_count[i], next, out_dev, b->threads, grid);
+            e = launch_qaoa<float>(b, cbi, true, t0, nt, next, out_dev, b->threads, grid);
         else
-            e = launch_qaoa<double>(b, b->d_seq_tasks, b->seq_begin[i], b->seq_count[i], next, out_dev, b->threads, grid);
+            e = launch_qaoa<double>(b, cbi, true, t0, nt, next, out_dev, b->threads, grid);
     }
     if (e != hipSuccess) return hip_fail(e, "qs_batch_qaoa_run_sequential");
     return QS_OK;
@@ -643,10 +680,10 @@ qs_status qs_batch_autotune(qs_batch *b, int *chosen, double *best_ms)
     double *tmp = nullptr;
     hipError_t e = hipMalloc(&tmp, sizeof(double) * b->count);
     if (e != hipSuccess) return hip_fail(e, "qs_batch_autotune: hipMalloc");
-    // launch shapes (threads, workgroups per CU) x chunk groupings
+    // launch shapes (threads, workgroups per CU) x chunk groupings x LDS chunk sizes
     const int shapes[][2] = {{256, 1}, {256, 2}, {256, 4}, {512, 1}, {512, 2}};
     const int nshape = (int)(sizeof(shapes) / sizeof(shapes[0]));
-    const int ncand = nshape * kNumGroups;
+    const int ncand = nshape * kNumGroups * kNumCB;
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
@@ -656,7 +693,9 @@ qs_status qs_batch_autotune(qs_batch *b, int *chosen, double *best_ms)
         float tbest = 1e30f;
         for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
             e = hipEventRecord(e0, b->stream);
-            if (e == hipSuccess) e = run_batch(b, tmp, shapes[c % nshape][0], shapes[c % nshape][1], c / nshape);
+            if (e == hipSuccess)
+                e = run_batch(b, tmp, shapes[c % nshape][0], shapes[c % nshape][1], (c / nshape) % kNumGroups,
+                              c / (nshape * kNumGroups));
             if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.f;
@@ -671,8 +710,9 @@ qs_status qs_batch_autotune(qs_batch *b, int *chosen, double *best_ms)
     if (e != hipSuccess) return hip_fail(e, "qs_batch_autotune");
     b->threads = shapes[bi % nshape][0];
     b->grid_per_cu = shapes[bi % nshape][1];
-    b->group = bi / nshape;
-    b->ntasks = b->grp_count[b->group];
+    b->group = (bi / nshape) % kNumGroups;
+    b->cbi = bi / (nshape * kNumGroups);
+    b->ntasks = b->grp_count[b->cbi][b->group];
     if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
     if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
     if (chosen) *chosen = bi;
@@ -691,7 +731,10 @@ qs_status qs_batch_free(qs_batch *b)
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
     if (b->gstream) (void)hipStreamDestroy(b->gstream);
-    for (void *p : {b->d_inst, b->d_tasks, b->d_seq_tasks, b->d_edges, b->d_tab, b->d_ctr})
+    for (int cbi = 0; cbi < qs::kNumCB; ++cbi)
+        for (void *p : {b->d_inst[cbi], b->d_tasks[cbi], b->d_seq_tasks[cbi]})
+            if (p) (void)hipFree(p);
+    for (void *p : {b->d_edges, b->d_tab, b->d_ctr})
         if (p) (void)hipFree(p);
     if (b->own_work)
         for (void *p : {b->d_work, b->d_czw})

@@ -93,8 +93,9 @@ def test_attach_rejects_host_memory_and_bad_workspace():
 
 
 def test_batch_workspace_size():
-    """States of instances above the in-LDS limit (13 qubits for complex64)
-    go to the workspace: 2^n amplitudes plus one cut-value byte each."""
+    """States of instances above the smaller of the two LDS chunk sizes the
+    autotuner may pick (12 qubits for complex64) go to the workspace: 2^n
+    amplitudes plus one cut-value byte each."""
     import numpy as np
     edges = np.array([0, 1, 1, 2, 2, 0], dtype=np.int32)
     g = np.array([0.3], dtype=np.float64)
@@ -110,6 +111,8 @@ def test_batch_workspace_size():
     amps = (1 << 14) + (1 << 16)
     assert nb.value == amps * 8 + amps
     assert L.qs_batch_qaoa_workspace_size(1, arr, 1, C.byref(nb)) == 0 and nb.value == 0
+    at13 = (qs.QaoaInst_C * 1)(inst(13))
+    assert L.qs_batch_qaoa_workspace_size(1, at13, 1, C.byref(nb)) == 0 and nb.value == (1 << 13) * 9
     bad = (qs.QaoaInst_C * 1)(inst(21))
     assert L.qs_batch_qaoa_workspace_size(1, bad, 1, C.byref(nb)) == -1
     assert L.qs_batch_qaoa_create(1, bad, 1, None, None, 0, None) == -1

@@ -80,7 +80,7 @@ def test_autotune_keeps_results(torch, batch512):
     insts, b, ref = batch512
     say("qaoa autotune")
     choice, ms = b.autotune()
-    assert 0 <= choice < 20 and ms > 0
+    assert 0 <= choice < 40 and ms > 0
     got = b.run(graph=True).cpu().numpy().copy()
     assert all(abs(got[i] - ref[i]) <= tol(q) for i, q in enumerate(insts))
 
