@@ -202,6 +202,27 @@ def bench_c64(torch, I, qs):
         log("complex64 32q %s: %.1f ms, ||d||2 %.3e" % (name, ms, math.sqrt(d2)))
     res["speedup_mfma_vs_vector"] = round(res["vector"]["ms"] / res["mfma"]["ms"], 3)
     del st, ref
+    torch.cuda.empty_cache()
+    # dense two-qubit gates, where 4-5-qubit fused ops do reach the matrix cores
+    n2 = 30
+    c2 = I.random_su4(n=n2, depth=20, seed=30020)
+    st2 = qs.State(n2, "c64")
+    pb2 = 2.0 * (1 << n2) * 8
+    su = {"workload": "Haar SU(4) on random pairs, 30 qubits, depth 20, seed 30020, complex64", "gates": len(c2)}
+    for name, mf in (("mfma", True), ("vector", False)):
+        p = qs.Plan(c2, kmax=5, dtype="c64", mfma=mf)
+        s = p.stats()
+        ms = _ms(torch, lambda: (st2.init_zero(), st2.apply_plan(p)))
+        ms_steps, kinds = st2.apply_plan_timed(p)
+        passes = s["blocks"] + s["swap_passes"]
+        su[name] = {"ms": round(ms, 2), "ops_mfma": s["ops_mfma"], "ops_dense": s["ops_dense"], "blocks": s["blocks"],
+                    "swap_passes": s["swap_passes"], "flops_per_amp": s["flops_per_amp"],
+                    "hbm_gbs": round(passes * pb2 / (float(ms_steps.sum()) * 1e-3) / 1e9, 1),
+                    "fp32_tflops": round(s["flops_per_amp"] * (1 << n2) / (float(ms_steps.sum()) * 1e-3) / 1e12, 2)}
+        log("complex64 30q SU(4) %s: %.1f ms (%d matrix-core ops)" % (name, ms, s["ops_mfma"]))
+    su["speedup_mfma_vs_vector"] = round(su["vector"]["ms"] / su["mfma"]["ms"], 3)
+    res["su4_30q"] = su
+    del st2
     return res
 
 
@@ -384,6 +405,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-planner comparison at 33 qubits (128 GiB)")
     ap.add_argument("--no-micro", action="store_true", help="skip the H-gate sweep and Table I gate benchmark")
+    ap.add_argument("--only", choices=("c64", "qaoa", "headline31", "micro", "learned"), default=None,
+                    help="run just this comparison and print its JSON object (for profiling one path)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no collectives); use --gpus 1", file=sys.stderr)
@@ -395,6 +418,11 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
+    if args.only:
+        legs = {"c64": bench_c64, "qaoa": bench_qaoa, "headline31": bench_headline31, "micro": bench_micro,
+                "learned": bench_learned}
+        print(json.dumps({"only": args.only, args.only: legs[args.only](torch, I, qs)}), flush=True)
+        return
     n, depth, seed, kmax = args.n, WORKLOAD["depth"], WORKLOAD["seed"], WORKLOAD["kmax"]
     circ = I.random_u3_2q(n=n, depth=depth, seed=seed)
     log("circuit: %d qubits, %d gates" % (n, len(circ)))

@@ -235,10 +235,61 @@ __device__ __forceinline__ void apply_mcx(V (&v)[1 << R], uint32_t ctrl, uint32_
     }
 }
 
-template <int R, typename V>
+// A CX with one control (the common case: one register bit on a given value) as a
+// compile-time exchange of the registers it pairs: after the case, the whole state is
+// pinned to registers (the switch's cases must not merge into an indexed array), so
+// the exchange costs one register move per dword instead of the masked exchange's
+// two selects and two XORs.
+template <int R, int T, int CB, int CV, typename V>
+__device__ __forceinline__ void apply_cx_c(V (&v)[1 << R])
+{
+#pragma unroll
+    for (int m = 0; m < (1 << R); ++m) {
+        if ((m >> T) & 1) continue;
+        if (((m >> CB) & 1) != CV) continue;
+        const V t = v[m];
+        v[m] = v[m | (1 << T)];
+        v[m | (1 << T)] = t;
+    }
+#pragma unroll
+    for (int m = 0; m < (1 << R); ++m) asm volatile("" : "+v"(v[m].x), "+v"(v[m].y));
+}
+
+template <int R, int T, typename V>
+__device__ __forceinline__ void cx_t(uint32_t cb, uint32_t cv, V (&v)[1 << R])
+{
+    switch (cb * 2 + cv) {
+#define QS_CXC(CBV, CVV)                                                                        \
+    case CBV * 2 + CVV:                                                                         \
+        if constexpr (CBV < R && CBV != T)                                                      \
+            apply_cx_c<R, T, (CBV < R && CBV != T ? CBV : (T + 1) % R), CVV, V>(v);             \
+        else                                                                                    \
+            __builtin_unreachable();                                                            \
+        break;
+    QS_CXC(0, 0) QS_CXC(0, 1) QS_CXC(1, 0) QS_CXC(1, 1) QS_CXC(2, 0) QS_CXC(2, 1) QS_CXC(3, 0) QS_CXC(3, 1)
+    QS_CXC(4, 0) QS_CXC(4, 1)
+#undef QS_CXC
+    default: __builtin_unreachable();
+    }
+}
+
+// (ONE_CTRL: the one-control cases have their compile-time paths; off in the variants
+// with dense ops, where the extra paths would push the register allocation into spills)
+template <int R, bool ONE_CTRL, typename V>
 __device__ __forceinline__ void mcx_dispatch(int var, uint32_t cval, V (&v)[1 << R])
 {
     const uint32_t ctrl = (uint32_t)var >> 3;
+    if (ONE_CTRL && __builtin_popcount(ctrl) == 1) {
+        const uint32_t cb = __builtin_ctz(ctrl), cv = cval ? 1u : 0u;
+        switch (var & 7) {
+        case 0: cx_t<R, 0, V>(cb, cv, v); return;
+        case 1: if constexpr (R > 1) { cx_t<R, (R > 1 ? 1 : 0), V>(cb, cv, v); return; } else __builtin_unreachable();
+        case 2: if constexpr (R > 2) { cx_t<R, (R > 2 ? 2 : 0), V>(cb, cv, v); return; } else __builtin_unreachable();
+        case 3: if constexpr (R > 3) { cx_t<R, (R > 3 ? 3 : 0), V>(cb, cv, v); return; } else __builtin_unreachable();
+        case 4: if constexpr (R > 4) { cx_t<R, (R > 4 ? 4 : 0), V>(cb, cv, v); return; } else __builtin_unreachable();
+        default: __builtin_unreachable();
+        }
+    }
     switch (var & 7) {
     case 0: apply_mcx<R, 0, V>(v, ctrl, cval); break;
     case 1: if constexpr (R > 1) apply_mcx<R, (R > 1 ? 1 : 0), V>(v, ctrl, cval); else __builtin_unreachable(); break;
@@ -680,7 +731,7 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
                     if constexpr (KMAX > 0) multi1_dispatch<R, F, V, const CF *>(variant, v, M);
                     else __builtin_unreachable();
                 } else if (kind == OP_MCX) {
-                    mcx_dispatch<R, V>(variant, __builtin_amdgcn_readfirstlane((uint32_t)op[3]), v);
+                    mcx_dispatch<R, KMAX == 0, V>(variant, __builtin_amdgcn_readfirstlane((uint32_t)op[3]), v);
                 } else if (kind == OP_ROT || kind == OP_ROTD) {
                     // one copy of the rotation paths for both kinds (code size)
                     rot_dispatch<R, F, V, const CF *>(variant, v, M);
