@@ -344,6 +344,12 @@ QS_API qs_status qs_batch_error(qs_batch *b, int *err);
  * re-captured).  Synchronises. */
 QS_API qs_status qs_batch_autotune(qs_batch *b, int *chosen, double *best_ms);
 
+/* Pin the configuration instead of tuning it: choice in 0..39, numbered as
+ * qs_batch_autotune's *chosen (shape + 5 * (grouping + 4 * chunk size index)).
+ * Host only; QS_EINVAL outside that range.  A captured graph is re-captured on
+ * the next graph run. */
+QS_API qs_status qs_batch_set_choice(qs_batch *b, int choice);
+
 /* ---- learned cost model (48 -> 128 -> 128 -> 1, FP32) --------------------- */
 /* The paper's planner minimises the number of passes over the state (Sec. IV,
  * Eq. 7); the learned planner (qs_fuse with planner = 1) scores candidate

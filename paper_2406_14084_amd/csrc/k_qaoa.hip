@@ -680,7 +680,8 @@ qs_status qs_batch_autotune(qs_batch *b, int *chosen, double *best_ms)
     double *tmp = nullptr;
     hipError_t e = hipMalloc(&tmp, sizeof(double) * b->count);
     if (e != hipSuccess) return hip_fail(e, "qs_batch_autotune: hipMalloc");
-    // launch shapes (threads, workgroups per CU) x chunk groupings x LDS chunk sizes
+    // launch shapes (threads, workgroups per CU) x chunk groupings x LDS chunk sizes (the
+    // same table and numbering as qs_batch_set_choice)
     const int shapes[][2] = {{256, 1}, {256, 2}, {256, 4}, {512, 1}, {512, 2}};
     const int nshape = (int)(sizeof(shapes) / sizeof(shapes[0]));
     const int ncand = nshape * kNumGroups * kNumCB;
@@ -717,6 +718,25 @@ qs_status qs_batch_autotune(qs_batch *b, int *chosen, double *best_ms)
     if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
     if (chosen) *chosen = bi;
     if (best_ms) *best_ms = best;
+    return QS_OK;
+}
+
+qs_status qs_batch_set_choice(qs_batch *b, int choice)
+{
+    using namespace qs;
+    constexpr int nshape = 5, ncand = nshape * kNumGroups * kNumCB;
+    static const int shapes[nshape][2] = {{256, 1}, {256, 2}, {256, 4}, {512, 1}, {512, 2}};
+    if (!b || choice < 0 || choice >= ncand) {
+        set_error("qs_batch_set_choice: null batch or choice outside 0.." + std::to_string(ncand - 1));
+        return QS_EINVAL;
+    }
+    b->threads = shapes[choice % nshape][0];
+    b->grid_per_cu = shapes[choice % nshape][1];
+    b->group = (choice / nshape) % kNumGroups;
+    b->cbi = choice / (nshape * kNumGroups);
+    b->ntasks = b->grp_count[b->cbi][b->group];
+    if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
     return QS_OK;
 }
 

@@ -93,6 +93,7 @@ SIGNATURES = {
     "qs_batch_qaoa_run_sequential": (C.c_int, [_P, _P]),
     "qs_batch_free": (C.c_int, [_P]),
     "qs_batch_autotune": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+    "qs_batch_set_choice": (C.c_int, [_P, C.c_int]),
     "qs_batch_error": (C.c_int, [_P, C.POINTER(C.c_int)]),
     "qs_costmodel_create": (C.c_int, [C.c_uint64, _P, C.POINTER(_P)]),
     "qs_costmodel_free": (C.c_int, [_P]),
@@ -470,6 +471,9 @@ class QaoaBatch:
         ms = C.c_double()
         check(lib().qs_batch_autotune(self.h, C.byref(ch), C.byref(ms)))
         return ch.value, ms.value
+
+    def set_choice(self, choice):
+        check(lib().qs_batch_set_choice(self.h, int(choice)))
 
     def error(self):
         e = C.c_int()

@@ -370,3 +370,51 @@ def test_permutation_ops_vs_oracle(torch, dtype, reg):
         st.apply_plan(p)
         d = max_abs_diff(st.numpy().astype(np.complex128), sim.run(c))
         assert d <= tol, d
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_pending_x_and_negative_controls_vs_oracle(torch, dtype):
+    """Rotations with angles above pi/4 leave an X pending to the block's store
+    (an address XOR), X gates only toggle it, and CX gates whose control carries it
+    run with the control on 0.  A 20-qubit circuit of large-angle RY/U3 gates,
+    X gates and CX/CZ gates on a random state matches the oracle, and X gates
+    alone on a random state are bit-exact (no op runs, the store permutes)."""
+    n = 20
+    rng = np.random.default_rng(21)
+    c = I.Circuit(n)
+    for _ in range(240):
+        k = int(rng.integers(0, 5))
+        if k == 0:
+            c.add("RY", (int(rng.integers(n)),), I.g_ry(float(rng.uniform(1.7, 3.1))))
+        elif k == 1:
+            c.add("U3", (int(rng.integers(n)),), I.g_u3(*rng.uniform(0, 6.3, 3)))
+        elif k == 2:
+            c.add("X", (int(rng.integers(n)),), I.g_x())
+        elif k == 3:
+            c.add("CX", tuple(int(x) for x in rng.choice(n, 2, replace=False)), I.g_cx())
+        else:
+            c.add("CZ", tuple(int(x) for x in rng.choice(n, 2, replace=False)), I.g_cz())
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    psi0 = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    psi0 /= np.linalg.norm(psi0)
+    if dtype == "c64":
+        psi0 = psi0.astype(np.complex64).astype(np.complex128)
+    st = qs.State(n, dtype)
+    p = qs.Plan(c, kmax=5, dtype=dtype)
+    say("pending X", dtype, len(c))
+    st.tensor.copy_(torch.from_numpy(psi0).to(tdt))
+    st.apply_plan(p)
+    want = psi0.copy()
+    sim.apply_circuit(want, c)
+    d = max_abs_diff(st.numpy().astype(np.complex128), want)
+    assert d <= (2e-6 if dtype == "c64" else TOL_C128), d
+    cx = I.Circuit(n)
+    for q in rng.integers(0, n, 40):
+        cx.add("X", (int(q),), I.g_x())
+    px = qs.Plan(cx, kmax=5, dtype=dtype)
+    assert px.stats()["flops_per_amp"] == 0
+    st.tensor.copy_(torch.from_numpy(psi0).to(tdt))
+    st.apply_plan(px)
+    want = psi0.copy()
+    sim.apply_circuit(want, cx)
+    assert np.array_equal(st.numpy().astype(np.complex128), want)

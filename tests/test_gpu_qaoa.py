@@ -85,6 +85,43 @@ def test_autotune_keeps_results(torch, batch512):
     assert all(abs(got[i] - ref[i]) <= tol(q) for i, q in enumerate(insts))
 
 
+def _between_batch(seed=77):
+    """Instances on both sides of the two LDS chunk sizes (11-14 qubits; odd sizes
+    on a ring with chords, even ones 3-regular)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for n in (11, 12, 13, 14, 13, 12):
+        if n % 2:
+            edges = [(i, (i + 1) % n) for i in range(n)] + [(i, (i + n // 2) % n) for i in range(0, n, 3)]
+            edges = sorted({(min(u, v), max(u, v)) for u, v in edges})
+        else:
+            edges = I.random_3regular(rng, n)
+        out.append(I.QaoaInstance(n, edges, rng.uniform(0, math.pi, 3), rng.uniform(0, math.pi, 3)))
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("choice", [6, 26])
+def test_each_lds_chunk_size(torch, dtype, choice):
+    """Both LDS chunk sizes the autotuner may pick (choice 6: 13 qubits for
+    complex64 / 12 for complex128; choice 26: one less; same launch shape and
+    grouping): an instance between the two sizes runs whole in LDS under one and
+    as chunk tasks in the workspace under the other; every <C> must match the
+    oracle either way, and the sequential schedule the batched one."""
+    insts = _between_batch()
+    ref = np.array([sim.qaoa_expectation(q) for q in insts])
+    say("qaoa set_choice", dtype, choice)
+    b = qs.QaoaBatch(insts, dtype)
+    b.set_choice(choice)
+    got = b.run(graph=False).cpu().numpy().copy()
+    seq = b.run_sequential().cpu().numpy().copy()
+    assert b.error() == 0
+    t = (lambda q: tol(q)) if dtype == "c64" else (lambda q: 1e-10)
+    assert all(abs(got[i] - ref[i]) <= t(q) for i, q in enumerate(insts)), (got, ref)
+    assert np.max(np.abs(seq - got)) <= 1e-9
+    b.close()
+
+
 def test_special_angles(torch):
     """gamma = 0 or beta = 0 leaves <C> = |E|/2 exactly in exact arithmetic."""
     rng = np.random.default_rng(2)

@@ -624,3 +624,72 @@ def test_replay_permutation_ops(dtype, reg):
     c = I.random_u3_2q(n=20, depth=8, seed=3, two="CX")
     s = qs.Plan(c, kmax=5, dtype=dtype).stats()
     assert s["ops_perm"] > 0 and s["ops_dense"][2] + s["ops_dense"][3] < s["ops_perm"], s
+
+
+def _flip_masks(p):
+    w, offs, R, C, mats = p.program()
+    return [(int(np.uint32(w[o + 6])) | (int(np.uint32(w[o + 7])) << 32), int(w[o + 3])) for o in offs]
+
+
+def test_pending_x_store_mask():
+    """A single-qubit gate with a rotation angle above pi/4 is run as X U' (U' well
+    conditioned) with the X left pending: later gates of the block on that qubit are
+    conjugated (a CX controlled by it becomes a CX on 0), X gates only toggle the
+    pending set (no op at all), and the block's store inverts the pending bits
+    (header words 6-7, with the load/store barrier flag).  The replay must match
+    the oracle, and the rotations' shear coefficients stay within |beta| <= 1/2,
+    |alpha| <= 1 (asserted by the replay)."""
+    n = 12
+    c = I.Circuit(n)
+    c.add("RY", (3,), I.g_ry(2.6))                  # theta/2 = 1.3 > pi/4: pending X on qubit 3
+    c.add("CX", (3, 7), I.g_cx())                    # control carries the pending X
+    c.add("X", (10,), I.g_x())                       # a bare X: no op
+    c.add("RY", (5,), I.g_ry(0.4))                   # small angle: no X
+    c.add("CZ", (3, 10), I.g_cz())                   # diagonal on two pending bits
+    c.add("U3", (7,), I.g_u3(2.9, 0.3, -1.1))
+    p = qs.Plan(c, kmax=5)
+    masks = _flip_masks(p)
+    assert any(m for m, _ in masks)
+    for m, flags in masks:
+        if m:
+            assert flags & 2                          # loads before stores
+    got = replay_plan(p, n)
+    assert np.max(np.abs(got - sim.run(c))) <= 1e-12
+    # X gates alone: no op and no arithmetic, the state permuted by the store only
+    cx = I.Circuit(n)
+    for q in (0, 4, 9, 11, 4):
+        cx.add("X", (q,), I.g_x())
+    px = qs.Plan(cx, kmax=5)
+    s = px.stats()
+    assert s["flops_per_amp"] == 0 and s["ops_perm"] == 0
+    rng = np.random.default_rng(3)
+    psi0 = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    want = psi0.copy()
+    sim.apply_circuit(want, cx)
+    assert np.array_equal(replay_plan(px, n, psi0=psi0), want)
+
+
+def test_negative_control_mcx_encoding():
+    """An X pending on a CX's control turns it into a CX on 0: the op word carries the
+    control values (word 3) within the control mask, and the kernel path exists."""
+    n = 10
+    c = I.Circuit(n)
+    c.add("RY", (1,), I.g_ry(2.8))
+    c.add("CX", (1, 2), I.g_cx())
+    c.add("RY", (2,), I.g_ry(0.3))
+    p = qs.Plan(c, kmax=5)
+    w, offs, R, C, mats = p.program()
+    found = []
+    for o in offs:
+        nph = int(w[o]); ph = o + PROG_HDR + 2 * C
+        for _ in range(nph):
+            nops = int(w[ph]); op = ph + PHASE_HDR + C + 2 * (C - R) + 2 * (1 << R)
+            for _ in range(nops):
+                if int(w[op]) & 0xff == 9:
+                    var = (int(w[op]) >> 8) & 0xff
+                    found.append((var >> 3, int(w[op + 3])))
+                op += OP_WORDS
+            ph = op
+    assert found and all(cv & ~ctrl == 0 for ctrl, cv in found)
+    assert any(cv != ctrl for ctrl, cv in found)      # at least one control on 0
+    assert np.max(np.abs(replay_plan(p, n) - sim.run(c))) <= 1e-12
