@@ -1690,6 +1690,16 @@ void encode_plan(Plan *p)
                     fuse_next[i] = 1;
                     --nenc;
                 }
+            // an odd count in a block without dense ops: split a fused rotation + diagonal
+            // back into its two ops rather than pad with a no-op (the no-op's path costs
+            // register copies; the split costs one more dispatch and no arithmetic)
+            if (bk == 0 && !bm && (nenc & 1))
+                for (size_t i = P.ops.size(); i-- > 0;)
+                    if (fuse_next[i]) {
+                        fuse_next[i] = 0;
+                        ++nenc;
+                        break;
+                    }
             w[hdr] = (int32_t)nenc;
             if (bk == 0 && !bm && (nenc & 1)) {
                 w[hdr] = (int32_t)nenc + 1;
