@@ -629,32 +629,36 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
         V v[NR];
         load_regs<R>(v, amps, chunk_base(c, cmask, n) | gin_t, bin);
         {
-            // the table, four words per thread in flight per round trip (sixteen for tables
-            // larger than four words per thread); the first round outside the loop (a loop
-            // header would wait for every load in flight, the chunk's included).  Indices are
-            // clamped into the table, so the loads need no per-lane branch; a group of words
-            // wholly past the table's end is skipped by a uniform test.
+            // the table, in 16-byte words (the planner pads it to whole ones and aligns every
+            // block's program): one per thread in flight per round trip, four for tables of
+            // more than one per thread; the first round outside the loop (a loop header would
+            // wait for every load in flight, the chunk's included).  Indices are clamped into
+            // the table, so the loads need no per-lane branch; a group of words wholly past
+            // the table's end is skipped by a uniform test.
             const int tab_off = prog[4], tab_words = prog[5];
+            const int n4 = tab_words >> 2;
             const int nt = (int)blockDim.x;
+            typedef int word4 __attribute__((ext_vector_type(4)));
+            const word4 *__restrict__ P4 = reinterpret_cast<const word4 *>(prog + tab_off);
+            word4 *L4 = reinterpret_cast<word4 *>(ltab);
             auto stage = [&](int b0, auto kgroups) __attribute__((always_inline)) {
                 constexpr int K = decltype(kgroups)::value;
-                int t[K];
+                word4 t[K];
 #pragma unroll
                 for (int k = 0; k < K; ++k)
-                    if (K == 4 || b0 + k * nt < tab_words)
-                        t[k] = prog[tab_off + min(b0 + k * nt + (int)tid, tab_words - 1)];
+                    if (K == 1 || b0 + k * nt < n4) t[k] = P4[min(b0 + k * nt + (int)tid, n4 - 1)];
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     const int i = b0 + k * nt + (int)tid;
-                    if (i < tab_words) ltab[i] = t[k];
+                    if (i < n4) L4[i] = t[k];
                 }
             };
-            if (tab_words) {
-                if (tab_words <= 4 * nt) {
-                    stage(0, std::integral_constant<int, 4>());
+            if (n4) {
+                if (n4 <= nt) {
+                    stage(0, std::integral_constant<int, 1>());
                 } else {
-                    stage(0, std::integral_constant<int, 16>());
-                    for (int b0 = 16 * nt; b0 < tab_words; b0 += 16 * nt) stage(b0, std::integral_constant<int, 16>());
+                    stage(0, std::integral_constant<int, 4>());
+                    for (int b0 = 4 * nt; b0 < n4; b0 += 4 * nt) stage(b0, std::integral_constant<int, 4>());
                 }
                 __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): the table writes are done
                 __builtin_amdgcn_s_barrier();

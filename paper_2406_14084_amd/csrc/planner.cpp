@@ -1884,6 +1884,8 @@ void encode_plan(Plan *p)
             }
         }
         while (w.size() % 4) w.push_back(0);
+        while (tab.size() % 4) tab.push_back(0);    // whole 16-byte words: staged as such, and every
+                                                    // block's program starts 16-byte aligned
         w[4] = (int32_t)w.size();
         w[5] = (int32_t)tab.size();
         w.insert(w.end(), tab.begin(), tab.end());

@@ -129,7 +129,8 @@ def replay_block(psi, w, n, R, mats, c64=False):
     tid = np.arange(1 << tb, dtype=np.int64)
     ph = PROG_HDR + 2 * C
     tab_off, tab_words = int(w[4]), int(w[5])
-    assert tab_off % 4 == 0 and (tab_words == 0 or tab_off >= ph)
+    # the kernel stages the table in 16-byte words from a 16-byte aligned block program
+    assert tab_off % 4 == 0 and tab_words % 4 == 0 and (tab_words == 0 or tab_off >= ph)
     # the table plus the exchange buffer (half the chunk in half-buffer blocks) must fit 160 KiB
     half = (int(w[3]) & 4) != 0
     assert ((8 if c64 else 16) << (C - 1 if half else C)) + 4 * tab_words <= 160 * 1024
@@ -361,6 +362,7 @@ def replay_plan(plan, n, psi0=None):
     else:
         psi = np.array(psi0, dtype=np.complex128)
     c64 = plan.stats()["dtype"] == 1
+    assert all(int(o) % 4 == 0 for o in offs)
     for o in offs:
         psi = replay_block(psi, w[o:], n, R, mats, c64)
     return psi
