@@ -541,16 +541,14 @@ __device__ __forceinline__ void store_regs(const V (&v)[1 << R], V *__restrict__
     }
 }
 
-// Chunk base: the chunk index spread over the physical qubits outside the chunk.
+// Chunk base: the chunk index spread over the physical qubits outside the chunk
+// (a deposit of c's bits into the clear bits of cmask, lowest first; one trip per
+// outside qubit, all scalar).
 __device__ __forceinline__ uint64_t chunk_base(uint64_t c, uint64_t cmask, int n)
 {
     uint64_t base = 0;
-    int bi = 0;
-    for (int q = 0; q < n; ++q) {
-        if ((cmask >> q) & 1ull) continue;
-        if ((c >> bi) & 1ull) base |= 1ull << q;
-        ++bi;
-    }
+    for (uint64_t m = ~cmask & ((n >= 64) ? ~0ull : ((1ull << n) - 1)); m; m &= m - 1, c >>= 1)
+        base |= (c & 1ull) << __builtin_ctzll(m);
     return base;
 }
 
@@ -627,7 +625,8 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
     const uint64_t c = (nbk % 8 == 0) ? (uint64_t)(blockIdx.x % 8) * (nbk / 8) + blockIdx.x / 8 : (uint64_t)blockIdx.x;
     {
         V v[NR];
-        load_regs<R>(v, amps, chunk_base(c, cmask, n) | gin_t, bin);
+        const uint64_t cbase = chunk_base(c, cmask, n);
+        load_regs<R>(v, amps, cbase | gin_t, bin);
         {
             // the table, in 16-byte words (the planner pads it to whole ones and aligns every
             // block's program): one per thread in flight per round trip, four for tables of
@@ -866,7 +865,7 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
         }
         // ---- store in the last layout, through P_out
         const uint64_t inv = (uint64_t)(uint32_t)prog[6] | ((uint64_t)(uint32_t)prog[7] << 32);
-        store_regs<R, std::is_same<F, double>::value>(v, amps, (chunk_base(c, cmask, n) | gout_t) ^ inv, bout);
+        store_regs<R, std::is_same<F, double>::value>(v, amps, (cbase | gout_t) ^ inv, bout);
     }
 }
 
