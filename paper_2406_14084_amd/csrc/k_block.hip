@@ -596,15 +596,9 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
     const bool half = (flags & 4) != 0;
     int *ltab = reinterpret_cast<int *>(lds_raw + ((size_t)sizeof(V) << (half ? C - 1 : C)));
 
-    // last phase (its layout is the store layout)
-    const int *phl = ph0;
-    {
-        const int *ph = ph0;
-        for (int p = 0; p < nph; ++p) {
-            phl = ph;
-            ph = ph + PHASE_HDR + C + 2 * tb + 2 * NR + OP_WORDS * ph[0];
-        }
-    }
+    // the last phase's layout is the store layout (its header offset is in the block
+    // header's flags word: no walk over the phases)
+    const int *phl = prog + ((uint32_t)flags >> 8);
     // global offsets: per thread (VGPR); per register bit j, the physical bit of
     // the load and store layouts (uniform) -- register offsets are rebuilt from
     // these in every chunk instead of being kept live in 2^R 64-bit registers.

@@ -1600,10 +1600,12 @@ void encode_plan(Plan *p)
         // stay what the exchange buffer allows (half buffer: three, whole buffer: two);
         // larger tables are read from device memory (L2) instead.
         const size_t tab_cap = std::min<size_t>(4096, (160u * 1024u - ((size_t)(c64 ? 8 : 16) << C)) / 4);
+        size_t last_hdr = 0;    // word offset of the last phase's header (the store layout)
         for (size_t ph = 0; ph < blk.phases.size(); ++ph) {
             const Phase &P = blk.phases[ph];
             uint64_t swz = (ph > 0) ? choose_swizzle(blk.phases[ph - 1].lay, P.lay, C, r) : 0;
             const size_t hdr = w.size();
+            last_hdr = hdr;
             w.push_back((int32_t)P.ops.size());
             w.push_back((int32_t)(uint32_t)(swz & 0xffffffffu));
             w.push_back((int32_t)(uint32_t)(swz >> 32));
@@ -1883,6 +1885,8 @@ void encode_plan(Plan *p)
                     }
             }
         }
+        if (last_hdr >= (1u << 23)) throw std::logic_error("block program too long");
+        w[3] |= (int32_t)((uint32_t)last_hdr << 8);
         while (w.size() % 4) w.push_back(0);
         while (tab.size() % 4) tab.push_back(0);    // whole 16-byte words: staged as such, and every
                                                     // block's program starts 16-byte aligned

@@ -334,6 +334,7 @@ def replay_block(psi, w, n, R, mats, c64=False):
         prev = ph
         ph = op
     Rb, T = layout(prev)
+    assert (int(np.uint32(w[3])) >> 8) == prev, "flags word must locate the last phase (store layout)"
     # pending X gates: the store inverts these physical bits of every address
     inv = (int(np.uint32(w[6])) | (int(np.uint32(w[7])) << 32))
     assert inv & ~sum(1 << q for q in Pout) == 0
