@@ -402,6 +402,14 @@ __device__ __forceinline__ uint32_t thread_local_bits(uint32_t tid, const int *_
     return l;
 }
 
+// physical offset of a local index (branch-free, P read by scalar loads)
+__device__ __forceinline__ uint64_t local_to_phys(uint32_t l, const int *__restrict__ P, int C)
+{
+    uint64_t o = 0;
+    for (int b = 0; b < C; ++b) o |= (uint64_t)((l >> b) & 1u) << P[b];
+    return o;
+}
+
 // bits of v selected by mask, packed to the low end (ascending)
 __device__ __forceinline__ uint32_t pext_u32(uint32_t v, uint32_t mask)
 {
@@ -412,14 +420,6 @@ __device__ __forceinline__ uint32_t pext_u32(uint32_t v, uint32_t mask)
     return r;
 }
 
-
-// physical offset of a local index (branch-free, P read by scalar loads)
-__device__ __forceinline__ uint64_t local_to_phys(uint32_t l, const int *__restrict__ P, int C)
-{
-    uint64_t o = 0;
-    for (int b = 0; b < C; ++b) o |= (uint64_t)((l >> b) & 1u) << P[b];
-    return o;
-}
 
 // XOR swizzle of an LDS slot (linear, bijective): local bits 4.. fold into
 // the low nibble (nibble b-4 of swlo/swhi), bit 3 folds into bits 0-2
@@ -582,13 +582,13 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
     const int C = prog[1];
     const int flags = prog[3];
     const int tb = C - R;
-    const int *__restrict__ Pin = prog + PROG_HDR;
-    const int *__restrict__ Pout = prog + PROG_HDR + C;
     const uint32_t tid = threadIdx.x;
     const int *ph0 = prog + PROG_HDR + 2 * C;
 
-    uint64_t cmask = 0;
-    for (int b = 0; b < C; ++b) cmask |= 1ull << Pin[b];
+    // the load map the planner puts right before the table: what would otherwise be derived
+    // from the first layout through chains of dependent scalar loads before the first loads
+    const int *__restrict__ mp = prog + prog[4] - kMapWords;
+    const uint64_t cmask = (uint64_t)(uint32_t)mp[26] | ((uint64_t)(uint32_t)mp[27] << 32);
 
     // per-lane data of diagonal ops: staged once into LDS, after the exchange buffer
     // (half the chunk when every exchange of the block runs in two rounds); filled
@@ -596,19 +596,20 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
     const bool half = (flags & 4) != 0;
     int *ltab = reinterpret_cast<int *>(lds_raw + ((size_t)sizeof(V) << (half ? C - 1 : C)));
 
-    // the last phase's layout is the store layout (its header offset is in the block
-    // header's flags word: no walk over the phases)
+    // global offsets: per thread (VGPR); per register bit j, its physical position when
+    // loading and when storing (uniform) -- register offsets are rebuilt from these in every
+    // chunk instead of being kept live in 2^R 64-bit registers.  The store side's thread
+    // part comes from the last phase's layout (its header offset is in the flags word),
+    // which measured faster than taking it from a map as well (that spilled registers).
     const int *phl = prog + ((uint32_t)flags >> 8);
-    // global offsets: per thread (VGPR); per register bit j, the physical bit of
-    // the load and store layouts (uniform) -- register offsets are rebuilt from
-    // these in every chunk instead of being kept live in 2^R 64-bit registers.
-    const uint64_t gin_t = local_to_phys(thread_local_bits(tid, ph0 + PHASE_HDR + R, tb), Pin, C);
-    const uint64_t gout_t = local_to_phys(thread_local_bits(tid, phl + PHASE_HDR + R, tb), Pout, C);
+    const uint64_t gout_t = local_to_phys(thread_local_bits(tid, phl + PHASE_HDR + R, tb), prog + PROG_HDR + C, C);
+    uint64_t gin_t = 0;
+    for (int j = 0; j < tb; ++j) gin_t |= (uint64_t)((tid >> j) & 1u) << mp[j];
     int bin[R], bout[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-        bin[j] = Pin[ph0[PHASE_HDR + j]];
-        bout[j] = Pout[phl[PHASE_HDR + j]];
+        bin[j] = mp[16 + j];
+        bout[j] = mp[21 + j];
     }
     const bool hazard = (flags & 2) && nph == 1;
 

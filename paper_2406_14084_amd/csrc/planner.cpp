@@ -1888,6 +1888,23 @@ void encode_plan(Plan *p)
         if (last_hdr >= (1u << 23)) throw std::logic_error("block program too long");
         w[3] |= (int32_t)((uint32_t)last_hdr << 8);
         while (w.size() % 4) w.push_back(0);
+        {
+            // load/store map (kMapWords words, a multiple of 4, right before the table):
+            // what the kernel would otherwise derive from the layouts before its first loads
+            if (C - r > 16 || r > 5) throw std::logic_error("layout too large for the load/store map");
+            const Layout &l0 = blk.phases.front().lay, &l1 = blk.phases.back().lay;
+            std::vector<int32_t> mp(kMapWords, 0);
+            uint64_t cm = 0;
+            for (int b = 0; b < C; ++b) cm |= 1ull << blk.P_in[b];
+            for (int j = 0; j < C - r; ++j) mp[j] = blk.P_in[l0.T[j]];
+            for (int j = 0; j < r; ++j) {
+                mp[16 + j] = blk.P_in[l0.R[j]];
+                mp[21 + j] = blk.P_out[l1.R[j]];
+            }
+            mp[26] = (int32_t)(uint32_t)(cm & 0xffffffffu);
+            mp[27] = (int32_t)(uint32_t)(cm >> 32);
+            w.insert(w.end(), mp.begin(), mp.end());
+        }
         while (tab.size() % 4) tab.push_back(0);    // whole 16-byte words: staged as such, and every
                                                     // block's program starts 16-byte aligned
         w[4] = (int32_t)w.size();

@@ -47,6 +47,8 @@ enum OpKind {
 // words of the per-nibble tables of an exchange's thread-bit words (write and read side each:
 // 16 for thread bits 0-3, 16 for bits 4-7, 2 for bit 8)
 constexpr int kNibWords = 34;
+// words of the load/store map right before a block's table (see the encoding below)
+constexpr int kMapWords = 28;
 
 struct Op {
     int kind = OP_DENSE;
@@ -121,7 +123,12 @@ qs_status build_plan_search(const qs_circuit *c, int kmax, const qs_plan_opts *o
 //   [0] nphases, [1] C, [2] r, [3] flags (bit 0 swap pass, bit 1 P_out != P_in,
 //       bit 2 every exchange runs in two rounds through half the LDS buffer; bits 8-31 the
 //       word offset of the last phase's header from the block start: the store layout)
-//   [4] table offset (words from block start, multiple of 4), [5] table words,
+//   [4] table offset (words from block start, multiple of 4), [5] table words; the
+//       kMapWords words before the table are the load/store map: [0..16) physical
+//       position of thread bit j when loading (P_in of the first phase's T[j]), [16..21)
+//       physical position of register bit j when loading (P_in of the first phase's
+//       R[j]), [21..26) when storing (P_out of the last phase's R[j]), [26], [27] the
+//       chunk's physical-qubit mask (low, high word); unused entries 0
 //   [6], [7] store inversion mask (physical bits, low / high word): the store writes the
 //       amplitude of index x at x ^ mask (pending X gates of the block)
 //   [8 .. 8+C)        P_in
