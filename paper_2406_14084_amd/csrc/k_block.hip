@@ -393,23 +393,6 @@ __device__ __forceinline__ void mfma_dispatch(int mask, c64 (&v)[32], const floa
 }
 #undef QS_MFMA_CASE
 
-// local index (within the chunk) of thread tid's register 0 in a layout:
-// thread bit j <-> local bit T[j]
-__device__ __forceinline__ uint32_t thread_local_bits(uint32_t tid, const int *__restrict__ T, int tb)
-{
-    uint32_t l = 0;
-    for (int j = 0; j < tb; ++j) l |= ((tid >> j) & 1u) << T[j];
-    return l;
-}
-
-// physical offset of a local index (branch-free, P read by scalar loads)
-__device__ __forceinline__ uint64_t local_to_phys(uint32_t l, const int *__restrict__ P, int C)
-{
-    uint64_t o = 0;
-    for (int b = 0; b < C; ++b) o |= (uint64_t)((l >> b) & 1u) << P[b];
-    return o;
-}
-
 // bits of v selected by mask, packed to the low end (ascending)
 __device__ __forceinline__ uint32_t pext_u32(uint32_t v, uint32_t mask)
 {
@@ -585,8 +568,9 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
     const uint32_t tid = threadIdx.x;
     const int *ph0 = prog + PROG_HDR + 2 * C;
 
-    // the load map the planner puts right before the table: what would otherwise be derived
-    // from the first layout through chains of dependent scalar loads before the first loads
+    // the load/store map the planner puts right before the table: what would otherwise be
+    // derived from the first and last layouts through chains of dependent scalar loads
+    // before the first loads
     const int *__restrict__ mp = prog + prog[4] - kMapWords;
     const uint64_t cmask = (uint64_t)(uint32_t)mp[26] | ((uint64_t)(uint32_t)mp[27] << 32);
 
@@ -598,11 +582,10 @@ void k_block(typename AmpOf<F>::type *__restrict__ amps,
 
     // global offsets: per thread (VGPR); per register bit j, its physical position when
     // loading and when storing (uniform) -- register offsets are rebuilt from these in every
-    // chunk instead of being kept live in 2^R 64-bit registers.  The store side's thread
-    // part comes from the last phase's layout (its header offset is in the flags word),
-    // which measured faster than taking it from a map as well (that spilled registers).
-    const int *phl = prog + ((uint32_t)flags >> 8);
-    const uint64_t gout_t = local_to_phys(thread_local_bits(tid, phl + PHASE_HDR + R, tb), prog + PROG_HDR + C, C);
+    // chunk instead of being kept live in 2^R 64-bit registers.  (The two thread loops stay
+    // separate, store side first: one joint loop spilled registers in some variants.)
+    uint64_t gout_t = 0;
+    for (int j = 0; j < tb; ++j) gout_t |= (uint64_t)((tid >> j) & 1u) << mp[28 + j];
     uint64_t gin_t = 0;
     for (int j = 0; j < tb; ++j) gin_t |= (uint64_t)((tid >> j) & 1u) << mp[j];
     int bin[R], bout[R];

@@ -1896,7 +1896,10 @@ void encode_plan(Plan *p)
             std::vector<int32_t> mp(kMapWords, 0);
             uint64_t cm = 0;
             for (int b = 0; b < C; ++b) cm |= 1ull << blk.P_in[b];
-            for (int j = 0; j < C - r; ++j) mp[j] = blk.P_in[l0.T[j]];
+            for (int j = 0; j < C - r; ++j) {
+                mp[j] = blk.P_in[l0.T[j]];
+                mp[28 + j] = blk.P_out[l1.T[j]];
+            }
             for (int j = 0; j < r; ++j) {
                 mp[16 + j] = blk.P_in[l0.R[j]];
                 mp[21 + j] = blk.P_out[l1.R[j]];

@@ -48,7 +48,7 @@ enum OpKind {
 // 16 for thread bits 0-3, 16 for bits 4-7, 2 for bit 8)
 constexpr int kNibWords = 34;
 // words of the load/store map right before a block's table (see the encoding below)
-constexpr int kMapWords = 28;
+constexpr int kMapWords = 44;
 
 struct Op {
     int kind = OP_DENSE;
@@ -128,7 +128,8 @@ qs_status build_plan_search(const qs_circuit *c, int kmax, const qs_plan_opts *o
 //       position of thread bit j when loading (P_in of the first phase's T[j]), [16..21)
 //       physical position of register bit j when loading (P_in of the first phase's
 //       R[j]), [21..26) when storing (P_out of the last phase's R[j]), [26], [27] the
-//       chunk's physical-qubit mask (low, high word); unused entries 0
+//       chunk's physical-qubit mask (low, high word), [28..44) physical position of thread
+//       bit j when storing (P_out of the last phase's T[j]); unused entries 0
 //   [6], [7] store inversion mask (physical bits, low / high word): the store writes the
 //       amplitude of index x at x ^ mask (pending X gates of the block)
 //   [8 .. 8+C)        P_in

@@ -18,7 +18,7 @@ from paper_2406_14084_amd import inputs as I
 from paper_2406_14084_amd import qs
 
 PROG_HDR, PHASE_HDR, OP_WORDS = 8, 4, 4
-MAP_WORDS = 28   # words of the load/store map before a block's table
+MAP_WORDS = 44   # words of the load/store map before a block's table
 
 
 def _pdep(v, mask):
@@ -151,18 +151,17 @@ def replay_block(psi, w, n, R, mats, c64=False):
     # it; it must agree with the first and last phases' layouts
     mp = [int(x) for x in w[tab_off - MAP_WORDS:tab_off]]
     assert (mp[26] & 0xffffffff) | ((mp[27] & 0xffffffff) << 32) == sum(1 << q for q in Pin)
-    assert all(x == 0 for x in mp[tb:16] + mp[16 + R:21] + mp[21 + R:26])
+    assert all(x == 0 for x in mp[tb:16] + mp[16 + R:21] + mp[21 + R:26] + mp[28 + tb:44])
 
-    def midx(T, P, rcol):
-        # thread part from a layout (T, P) or, with P None, from the map's thread columns
+    def midx(tcol, rcol):
         g = np.zeros_like(tid)
         for j in range(tb):
-            g |= ((tid >> j) & 1) << (mp[j] if P is None else P[T[j]])
+            g |= ((tid >> j) & 1) << mp[tcol + j]
         o = np.array([sum(1 << mp[rcol + j] for j in range(R) if (m >> j) & 1) for m in range(NR)], dtype=np.int64)
         return (base[:, None] | g[None, :])[:, :, None] | o[None, None, :]
 
     Rb, T = layout(ph)
-    li = midx(T, None, 16)
+    li = midx(0, 16)
     assert np.array_equal(li, gidx(Rb, T, Pin)), "load map disagrees with the first layout"
     assert li.min() >= 0 and li.max() < (1 << n)
     assert np.unique(li).size == li.size == (1 << n), "load is not a bijection"
@@ -355,7 +354,7 @@ def replay_block(psi, w, n, R, mats, c64=False):
     inv = (int(np.uint32(w[6])) | (int(np.uint32(w[7])) << 32))
     assert inv & ~sum(1 << q for q in Pout) == 0
     assert tab_off - MAP_WORDS >= ph, "load/store map overlaps the phases"
-    so = midx(T, Pout, 21) ^ inv
+    so = midx(28, 21) ^ inv
     assert np.array_equal(so, gidx(Rb, T, Pout) ^ inv), "store map disagrees with the last layout"
     assert so.min() >= 0 and so.max() < (1 << n)
     assert np.unique(so).size == so.size == (1 << n), "store is not a bijection"
