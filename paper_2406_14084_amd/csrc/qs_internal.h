@@ -122,7 +122,8 @@ qs_status build_plan_search(const qs_circuit *c, int kmax, const qs_plan_opts *o
 // Program encoding read by the blocked kernel (int32 words per block):
 //   [0] nphases, [1] C, [2] r, [3] flags (bit 0 swap pass, bit 1 P_out != P_in,
 //       bit 2 every exchange runs in two rounds through half the LDS buffer; bits 8-31 the
-//       word offset of the last phase's header from the block start: the store layout)
+//       word offset of the last phase's header from the block start: the store layout, for
+//       validators -- the kernel takes its store addresses from the map below)
 //   [4] table offset (words from block start, multiple of 4), [5] table words; the
 //       kMapWords words before the table are the load/store map: [0..16) physical
 //       position of thread bit j when loading (P_in of the first phase's T[j]), [16..21)
