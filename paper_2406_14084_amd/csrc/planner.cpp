@@ -1531,6 +1531,18 @@ static void check_program(const Plan &p)
             }
             ph = op;
         }
+        // the load/store map (the kernel's only source of global addresses) sits between the
+        // phases and the table and agrees with the first and last phases' layouts
+        const int32_t *mp = w + w[4] - kMapWords;
+        const int32_t *l0 = w + PROG_HDR + 2 * C + PHASE_HDR, *l1 = w + ((uint32_t)w[3] >> 8) + PHASE_HDR;
+        const int32_t *Pin = w + PROG_HDR, *Pout = w + PROG_HDR + C;
+        bool mok = w[4] % 4 == 0 && mp >= ph && tb <= 16 && r <= 5;
+        uint64_t cm = 0;
+        for (int b2 = 0; mok && b2 < C; ++b2) cm |= 1ull << Pin[b2];
+        mok = mok && (uint32_t)mp[26] == (uint32_t)cm && (uint32_t)mp[27] == (uint32_t)(cm >> 32);
+        for (int j = 0; mok && j < tb; ++j) mok = mp[j] == Pin[l0[r + j]] && mp[28 + j] == Pout[l1[r + j]];
+        for (int j = 0; mok && j < r; ++j) mok = mp[16 + j] == Pin[l0[j]] && mp[21 + j] == Pout[l1[j]];
+        if (!mok) throw std::logic_error("block " + std::to_string(b) + ": load/store map disagrees with its layouts");
     }
 }
 
