@@ -713,3 +713,30 @@ def test_negative_control_mcx_encoding():
     assert found and all(cv & ~ctrl == 0 for ctrl, cv in found)
     assert any(cv != ctrl for ctrl, cv in found)      # at least one control on 0
     assert np.max(np.abs(replay_plan(p, n) - sim.run(c))) <= 1e-12
+
+
+def test_replay_rejects_a_wrong_load_store_map():
+    """The kernel takes every global address from the load/store map before the table;
+    the replay checks it against the layouts, so a map with two thread-bit positions
+    exchanged, a register-bit position changed or a wrong chunk mask must be caught
+    (mistakes planted in a host copy of the encoded program)."""
+    n = 14
+    c = I.random_u3_2q(n=n, depth=6, seed=21)
+    p = qs.Plan(c, kmax=5)
+    w, offs, R, C, mats = p.program()
+    o = int(offs[0])
+    blk = np.array(w[o:], copy=True)
+    psi = np.zeros(1 << n, dtype=np.complex128)
+    psi[0] = 1
+    replay_block(psi, blk, n, R, mats)            # the encoded map passes
+    mp0 = int(blk[4]) - MAP_WORDS
+    for plant in ("swap_thread_bits", "register_bit", "mask"):
+        bad = blk.copy()
+        if plant == "swap_thread_bits":
+            bad[mp0], bad[mp0 + 1] = blk[mp0 + 1], blk[mp0]
+        elif plant == "register_bit":
+            bad[mp0 + 21] = blk[mp0 + 22]
+        else:
+            bad[mp0 + 26] = int(blk[mp0 + 26]) ^ 1
+        with pytest.raises(AssertionError):
+            replay_block(psi, bad, n, R, mats)
