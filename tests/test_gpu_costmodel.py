@@ -182,7 +182,8 @@ def test_learned_vs_heuristic_33q(torch):
     geometry, also the learned planner's fallback) and the paper's objective
     over the same candidates (fewest passes, Eq. 7).  The learned plan must
     not lose to the heuristic and must beat the pass-count choice; all three
-    give the same amplitudes (4096 sampled indices and the norm)."""
+    give the same amplitudes (4096 sampled indices and the norm), and the learned
+    plans of the circuit and of its inverse return the state to |0...0>."""
     model = trained_model()
     n = 33
     c = I.random_su4(n=n, depth=60, seed=33005)
@@ -208,6 +209,19 @@ def test_learned_vs_heuristic_33q(torch):
     assert max_abs_diff(samp["passes"], samp["heuristic"]) <= TOL_C128
     assert t["learned"] <= 1.02 * t["heuristic"]
     assert t["learned"] <= 0.95 * t["passes"]
+    # every amplitude of the learned plans, in one buffer: the learned plan of the circuit,
+    # then the learned plan of its inverse, must return |0...0> (a_0 = 1 with the norm 1
+    # leaves at most |norm - |a_0|^2| for all other amplitudes together)
+    pinv = qs.Plan(c.inverse(), kmax=5, planner=1, cost_model=model)
+    st.init_zero()
+    st.apply_plan(plans["learned"])
+    st.apply_plan(pinv)
+    a0 = complex(st.amplitudes(0, 1)[0])
+    norm = st.expect([(0, 0, 1.0)])
+    far = np.abs(st.tensor[idx[idx != 0]].cpu().numpy()).max()
+    say("33q learned plan then learned inverse: |a0 - 1| %.2e  norm-1 %.2e  max sampled |a| %.2e"
+        % (abs(a0 - 1), norm - 1, far))
+    assert abs(a0 - 1.0) <= 1e-10 and abs(norm - 1.0) <= 1e-10 and far <= 1e-10
 
 
 def test_learned_vs_heuristic_c64_30q(torch):
