@@ -39,7 +39,7 @@ META_PATH = os.path.join(_HERE, "data", "costmodel_meta.json")
 # whole); the harvest samples plans from the same grid.
 GRID_C = (11, 12, 13)
 GRID_R = (3, 4, 5)
-GRID_L = (4, 5)
+GRID_L = (3, 4, 5)
 GRID_K = (2, 3, 4, 5)
 
 

@@ -246,7 +246,7 @@ qs_status build_plan_search(const qs_circuit *c, int kmax, const qs_plan_opts *o
     if (base.reg_qubits) rs = {base.reg_qubits};
     else rs = {3, 4, 5};
     if (base.low_qubits) Ls = {base.low_qubits};
-    else Ls = {4, 5};
+    else Ls = {3, 4, 5};
     for (int k = std::max(1, kmax - 3); k <= kmax; ++k) ks.push_back(k);
     std::vector<int> mfs{base.no_mfma};
     if (base.dtype == QS_C64 && !base.no_mfma) mfs.push_back(1);     // matrix cores on and off

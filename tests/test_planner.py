@@ -217,7 +217,7 @@ def test_pass_count_planner_minimises_passes():
     cands = []
     for C in (11, 12, 13):
         for r in (3, 4, 5):
-            for L in (4, 5):
+            for L in (3, 4, 5):
                 for k in (2, 3, 4, 5):
                     cands.append(passes(qs.Plan(c, kmax=k, chunk_qubits=C, reg_qubits=r, low_qubits=L).stats()))
     assert passes(s) == min(cands + [passes(qs.Plan(c, kmax=5).stats())])
